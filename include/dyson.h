@@ -1,0 +1,184 @@
+/*
+ * dyson.h -- C ABI of the MI355X library that computes the local Green's
+ * function G_ii(i w_k) = [H(i w_k)^{-1}]_ii of the lattice Dyson matrix by the
+ * Lanczos-based low-rank correction method (Carrier, Tang, Saad, Freericks,
+ * arXiv:1102.3137).
+ *
+ * Problem statement (Sec. I, eq. (1)): on a hypercubic lattice with
+ * nearest-neighbour bonds, H_ij = t for every bond and
+ * H_ii = i w_k + mu - V_i - Sigma_i(i w_k).  Only diag(H^{-1}) is wanted.
+ *
+ * Conventions shared by every entry point
+ *   - Sites are in natural order, x fastest: i = x + Lx*(y + Ly*z).
+ *   - Complex arrays are interleaved (re, im) float64, frequency-major:
+ *     element (k, i) of a [K][N] array sits at doubles 2*(k*N+i), 2*(k*N+i)+1.
+ *   - Pointers named d_* are DEVICE pointers (hipMalloc'ed or any device
+ *     memory visible to the plan's device); h_* are host pointers.
+ *   - The caller owns every buffer passed in; the library never frees or
+ *     keeps them beyond the call.  The library owns contexts and plans.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered; a call returns after its work is enqueued and, for
+ *     the solve entry points, after it has completed (they poll device-side
+ *     convergence flags).
+ *   - Errors are status codes; nothing throws across the ABI.  On error the
+ *     output buffers are left untouched or partially written and must not
+ *     be used; dyson_last_error() gives a message (thread-local).
+ *   - Validation returns DYSON_EINVAL: dim not in {1,2}, any L < 1, K < 1,
+ *     w_k <= 0, non-finite input, or Im(i w_k - Sigma_i) <= 0 (the last
+ *     keeps Im H positive definite, so H and every principal submatrix are
+ *     non-singular and the pivot-free factorizations below exist).
+ */
+#ifndef DYSON_MI355X_H
+#define DYSON_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DYSON_OK = 0,
+  DYSON_EINVAL = 1,      /* invalid argument or input value */
+  DYSON_ENOMEM = 2,      /* device allocation failed */
+  DYSON_EBREAKDOWN = 3,  /* Lanczos breakdown not cured by restarts */
+  DYSON_ENOCONV = 4,     /* an inner solve hit its iteration cap */
+  DYSON_EDEVICE = 5,     /* HIP runtime error */
+  DYSON_EUNSUPPORTED = 6 /* valid request this build does not implement */
+} dyson_status;
+
+/* Lattice geometry and hopping (eq. (1)).  Open boundaries only. */
+typedef struct {
+  int dim;       /* 1 or 2 */
+  int L[3];      /* extents, unused axes = 1; x fastest */
+  double t;      /* hopping: H_ij = t on each nearest-neighbour bond */
+  double mu;     /* chemical potential in H_ii */
+} dyson_lattice;
+
+enum { DYSON_PART_NESTED = 0, DYSON_PART_SINGLE = 1 };
+enum { DYSON_PREC_FP64 = 0, DYSON_PREC_MIXED = 1 };
+
+/* Method options.  Zero-initialise and set what you need; zero fields take
+ * the defaults given in brackets. */
+typedef struct {
+  int leaf_edge;      /* subdomain edge s: separators at p with (p+1)%s==0 [16]; 2..16 */
+  int partition;      /* DYSON_PART_NESTED: recursive bisection, alternating axes
+                         (end of Sec. II.C); DYSON_PART_SINGLE: one level with
+                         every separator at once (Fig. 1) [NESTED] */
+  int precision;      /* DYSON_PREC_FP64, or DYSON_PREC_MIXED: complex64
+                         subdomain factors in the inner preconditioner, FP64
+                         residuals and FP64 Lanczos [FP64] */
+  int max_rank;       /* cap on Lanczos steps per domain (truncated rank); 0 = full [0] */
+  int extra_steps;    /* steps allowed beyond the interface size m (Sec. II.C) [10] */
+  int max_inner_iters;/* iteration cap of each inner solve [2000] */
+  double inner_tol;   /* relative residual of the inner solves [1e-13] */
+  double lanczos_tol; /* stop when |r|_2 <= lanczos_tol*|u|_2 [1e-10] */
+  uint64_t seed;      /* seed of the Lanczos start vectors [0x5eed] */
+  int profile;        /* 1: time the hot kernels with HIP events into the report */
+} dyson_opts;
+
+/* Filled by dyson_solve when report != NULL. */
+typedef struct {
+  double t_total_ms;        /* host wall time of the call */
+  int levels;               /* correction levels run */
+  int max_rank_used;        /* largest Lanczos step count of any domain */
+  long long lanczos_steps;  /* sum over (domain, frequency) of Lanczos steps */
+  long long inner_iters;    /* sum over inner solves and items of iterations */
+  int inner_iters_max;      /* worst single inner solve */
+  int restarts;             /* breakdown restarts */
+  int truncated;            /* 1 if any domain stopped at max_rank before exhaustion */
+  /* per-kernel-class timing (profile=1): 0 = inner-solve update/preconditioner,
+   * 1 = inner-solve stencil, 2 = re-orthogonalization, 3 = other */
+  double kern_ms[4];
+  long long kern_launches[4];
+  double kern_bytes[4];     /* algorithmic HBM bytes those launches moved */
+} dyson_report;
+
+typedef struct dyson_ctx dyson_ctx;
+typedef struct dyson_plan dyson_plan;
+
+/* Summary of a plan (the domain decomposition of eq. (4), recursively). */
+typedef struct {
+  int n_sites;        /* N */
+  int n_tiles;        /* subdomain tiles (one leaf each) */
+  int tile_sites;     /* padded sites per tile, s^dim */
+  int levels;         /* correction levels (0 = the whole lattice) */
+  int n_nodes[32];    /* correction domains per level */
+  int max_m[32];      /* largest interface size m per level */
+  long long sum_m[32];/* sum of m over the level's domains */
+} dyson_plan_info;
+
+/* Context on one HIP device.  device = ordinal. */
+dyson_status dyson_create(dyson_ctx** ctx, int device);
+dyson_status dyson_destroy(dyson_ctx* ctx);
+
+/* Build the domain decomposition (host only, integer work; Fig. 1, eq. (4),
+ * recursion at the end of Sec. II.C).  opts may be NULL for defaults. */
+dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat,
+                               const dyson_opts* opts, dyson_plan** plan);
+dyson_status dyson_plan_destroy(dyson_plan* plan);
+dyson_status dyson_plan_get_info(const dyson_plan* plan, dyson_plan_info* info);
+
+/* Host copies of the plan's site maps, natural order, length N each:
+ * h_depth[i]  = level at which site i becomes interface (separator), or, for
+ *               subdomain-interior sites, the depth of their leaf;
+ * h_is_sep[i] = 1 for separator sites, 0 for leaf-interior sites;
+ * h_tile[i]   = the tile (leaf) holding site i (tiles numbered in the
+ *               depth-first order of the domain tree). */
+dyson_status dyson_plan_get_maps(const dyson_plan* plan, int* h_depth,
+                                 int* h_is_sep, int* h_tile);
+
+/* Device memory a dyson_solve over K frequencies will allocate (bytes). */
+dyson_status dyson_footprint(const dyson_plan* plan, int K, size_t* bytes);
+
+/* Full hot path: diag(H(i w_k)^{-1}) for K frequencies.
+ * d_V [N] f64; d_omega [K] f64 (w_k > 0); d_sigma [K][N] complex
+ * (Sigma_i(i w_k)); d_G [K][N] complex output.  All device pointers.
+ * Steps: assemble d_i (eq. (1)); factor the subdomain blocks and take
+ * diag(B^{-1}) (eq. (13), first term); per level, bottom-up, bilinear Lanczos
+ * on X = H^{-1} - blkdiag(B^{-1},0) (eqs. (7)-(12)) with the streaming
+ * three-vector diagonal (after eq. (13)); combine and scatter. */
+dyson_status dyson_solve(dyson_plan* plan, int K, const double* d_V,
+                         const double* d_omega, const double* d_sigma,
+                         double* d_G, void* stream, dyson_report* report);
+
+/* ---- Stage entry points (the same kernels the solve runs), for testing ----
+ * All pointers are device pointers; the plan's workspace for K frequencies
+ * is (re)allocated as needed. */
+
+/* eq. (1): d_d [K][N] complex = i w_k + mu - V_i - Sigma_i(i w_k). */
+dyson_status dyson_assemble(dyson_plan* plan, int K, const double* d_V,
+                            const double* d_omega, const double* d_sigma,
+                            double* d_d, void* stream);
+
+/* eq. (13), first term: for every leaf subdomain block B_s (the lattice
+ * restricted to the leaf's sites), d_Gleaf[k][i] = [B_s(w_k)^{-1}]_ii for
+ * leaf sites and 0 for separator sites.  d_d as produced by dyson_assemble. */
+dyson_status dyson_leaf_diag(dyson_plan* plan, int K, const double* d_d,
+                             double* d_Gleaf, void* stream);
+
+/* eqs. (10)-(12): d_u = X_l d_q for every correction domain of level l at
+ * once, X_l = H_l^{-1} - blkdiag(B_l^{-1}, 0) with H_l the lattice restricted
+ * to each level-l domain and B_l its subdomains.  d_q [K][N] complex; entries
+ * outside level-l domains are ignored, those of d_u are set to 0. */
+dyson_status dyson_xmatvec(dyson_plan* plan, int level, int K,
+                           const double* d_d, const double* d_q, double* d_u,
+                           void* stream);
+
+/* One level of the correction: bilinear Lanczos on X_l for every level-l
+ * domain and frequency, adding diag(Q T Q^T) into d_Gacc [K][N] (complex,
+ * accumulated in place).  h_steps [K*n_nodes] (may be NULL) receives the
+ * Lanczos steps per (frequency, domain), domain-fastest. */
+dyson_status dyson_correct_level(dyson_plan* plan, int level, int K,
+                                 const double* d_d, double* d_Gacc,
+                                 int* h_steps, void* stream);
+
+const char* dyson_last_error(void);
+const char* dyson_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DYSON_MI355X_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of include/dyson.h (argument marshalling only).
+
+Functions keep the C names (dyson_create, dyson_plan_create, dyson_solve, ...).
+The `Plan` helper accepts torch tensors that live on the GPU and passes their
+data pointers and the current HIP stream; PyTorch provides device memory and
+streams, every computation runs in the HIP kernels of the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdyson_mi355x.so")
+
+PART_NESTED, PART_SINGLE = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+STATUS = {0: "DYSON_OK", 1: "DYSON_EINVAL", 2: "DYSON_ENOMEM", 3: "DYSON_EBREAKDOWN",
+          4: "DYSON_ENOCONV", 5: "DYSON_EDEVICE", 6: "DYSON_EUNSUPPORTED"}
+
+
+class DysonError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Lattice(C.Structure):
+    _fields_ = [("dim", C.c_int), ("L", C.c_int * 3), ("t", C.c_double), ("mu", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("leaf_edge", C.c_int), ("partition", C.c_int), ("precision", C.c_int),
+                ("max_rank", C.c_int), ("extra_steps", C.c_int), ("max_inner_iters", C.c_int),
+                ("inner_tol", C.c_double), ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
+                ("profile", C.c_int)]
+
+
+class Report(C.Structure):
+    _fields_ = [("t_total_ms", C.c_double), ("levels", C.c_int), ("max_rank_used", C.c_int),
+                ("lanczos_steps", C.c_longlong), ("inner_iters", C.c_longlong),
+                ("inner_iters_max", C.c_int), ("restarts", C.c_int), ("truncated", C.c_int),
+                ("kern_ms", C.c_double * 4), ("kern_launches", C.c_longlong * 4),
+                ("kern_bytes", C.c_double * 4)]
+
+    def as_dict(self):
+        return {"t_total_ms": self.t_total_ms, "levels": self.levels,
+                "max_rank_used": self.max_rank_used, "lanczos_steps": self.lanczos_steps,
+                "inner_iters": self.inner_iters, "inner_iters_max": self.inner_iters_max,
+                "restarts": self.restarts, "truncated": self.truncated,
+                "kern_ms": list(self.kern_ms), "kern_launches": list(self.kern_launches),
+                "kern_bytes": list(self.kern_bytes)}
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_sites", C.c_int), ("n_tiles", C.c_int), ("tile_sites", C.c_int),
+                ("levels", C.c_int), ("n_nodes", C.c_int * 32), ("max_m", C.c_int * 32),
+                ("sum_m", C.c_longlong * 32)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int)
+
+# (name, restype, argtypes) for every entry point of include/dyson.h
+SIGNATURES = [
+    ("dyson_create", C.c_int, [C.POINTER(_P), C.c_int]),
+    ("dyson_destroy", C.c_int, [_P]),
+    ("dyson_plan_create", C.c_int, [_P, C.POINTER(Lattice), C.POINTER(Opts), C.POINTER(_P)]),
+    ("dyson_plan_destroy", C.c_int, [_P]),
+    ("dyson_plan_get_info", C.c_int, [_P, C.POINTER(PlanInfo)]),
+    ("dyson_plan_get_maps", C.c_int, [_P, _I, _I, _I]),
+    ("dyson_footprint", C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
+    ("dyson_solve", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_assemble", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
+    ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
+    ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
+    ("dyson_correct_level", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _I, _P]),
+    ("dyson_last_error", C.c_char_p, []),
+    ("dyson_version", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1102_3137_amd.build`"
+                          " (there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise DysonError(status, load_library().dyson_last_error().decode())
+
+
+# thin wrappers with the C names --------------------------------------------
+def dyson_create(device: int = 0):
+    h = _P()
+    _check(load_library().dyson_create(C.byref(h), device))
+    return h
+
+
+def dyson_destroy(ctx):
+    _check(load_library().dyson_destroy(ctx))
+
+
+def dyson_plan_create(ctx, lat: Lattice, opts: Opts | None):
+    h = _P()
+    _check(load_library().dyson_plan_create(ctx, C.byref(lat),
+                                            C.byref(opts) if opts is not None else None,
+                                            C.byref(h)))
+    return h
+
+
+def dyson_plan_destroy(plan):
+    _check(load_library().dyson_plan_destroy(plan))
+
+
+def dyson_plan_get_info(plan) -> PlanInfo:
+    info = PlanInfo()
+    _check(load_library().dyson_plan_get_info(plan, C.byref(info)))
+    return info
+
+
+def dyson_plan_get_maps(plan, n_sites: int):
+    import numpy as np
+    depth = np.zeros(n_sites, np.int32)
+    is_sep = np.zeros(n_sites, np.int32)
+    tile = np.zeros(n_sites, np.int32)
+    ip = lambda a: a.ctypes.data_as(_I)  # noqa: E731
+    _check(load_library().dyson_plan_get_maps(plan, ip(depth), ip(is_sep), ip(tile)))
+    return depth, is_sep, tile
+
+
+def dyson_footprint(plan, K: int) -> int:
+    b = C.c_size_t()
+    _check(load_library().dyson_footprint(plan, K, C.byref(b)))
+    return int(b.value)
+
+
+def dyson_solve(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream, report: Report | None = None):
+    _check(load_library().dyson_solve(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                                      C.byref(report) if report is not None else None))
+
+
+def dyson_assemble(plan, K, V_ptr, omega_ptr, sigma_ptr, d_ptr, stream):
+    _check(load_library().dyson_assemble(plan, K, V_ptr, omega_ptr, sigma_ptr, d_ptr, stream))
+
+
+def dyson_leaf_diag(plan, K, d_ptr, G_ptr, stream):
+    _check(load_library().dyson_leaf_diag(plan, K, d_ptr, G_ptr, stream))
+
+
+def dyson_xmatvec(plan, level, K, d_ptr, q_ptr, u_ptr, stream):
+    _check(load_library().dyson_xmatvec(plan, level, K, d_ptr, q_ptr, u_ptr, stream))
+
+
+def dyson_correct_level(plan, level, K, d_ptr, G_ptr, steps_np, stream):
+    sp = steps_np.ctypes.data_as(_I) if steps_np is not None else None
+    _check(load_library().dyson_correct_level(plan, level, K, d_ptr, G_ptr, sp, stream))
+
+
+# torch-facing helper ---------------------------------------------------------
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan on one GPU.  Inputs and outputs are torch tensors on that GPU:
+    V float64 [N], omega float64 [K], sigma complex128 [K, N]; G complex128 [K, N]."""
+
+    def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
+                 precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
+                 inner_tol=1e-13, lanczos_tol=1e-10, seed=0x5EED, profile=False, device=0):
+        dims = tuple(int(x) for x in dims)
+        lat = Lattice()
+        lat.dim = len(dims)
+        for a in range(3):
+            lat.L[a] = dims[a] if a < len(dims) else 1
+        lat.t, lat.mu = float(t), float(mu)
+        o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
+                 inner_tol, lanczos_tol, seed, int(bool(profile)))
+        self.dims = dims
+        self.n_sites = 1
+        for x in dims:
+            self.n_sites *= x
+        self.ctx = dyson_create(device)
+        self.plan = dyson_plan_create(self.ctx, lat, o)
+        self.info = dyson_plan_get_info(self.plan)
+
+    def close(self):
+        if getattr(self, "plan", None):
+            dyson_plan_destroy(self.plan)
+            self.plan = None
+        if getattr(self, "ctx", None):
+            dyson_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self):
+        i = self.info
+        return [dict(n_nodes=i.n_nodes[l], max_m=i.max_m[l], sum_m=i.sum_m[l])
+                for l in range(i.levels)]
+
+    def maps(self):
+        return dyson_plan_get_maps(self.plan, self.n_sites)
+
+    def footprint(self, K):
+        return dyson_footprint(self.plan, K)
+
+    @staticmethod
+    def _c(x):
+        import torch
+        assert x.is_cuda and x.is_contiguous(), "device tensors required"
+        if x.is_complex():
+            assert x.dtype == torch.complex128
+        else:
+            assert x.dtype == torch.float64
+        return x
+
+    def solve(self, V, omega, sigma, G=None, report=False):
+        import torch
+        K = int(omega.shape[0])
+        if G is None:
+            G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
+        rep = Report()
+        dyson_solve(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)), _ptr(self._c(sigma)),
+                    _ptr(self._c(G)), _stream(), rep)
+        return (G, rep.as_dict()) if report else G
+
+    def assemble(self, V, omega, sigma):
+        import torch
+        K = int(omega.shape[0])
+        d = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
+        dyson_assemble(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)),
+                       _ptr(self._c(sigma)), _ptr(d), _stream())
+        return d
+
+    def leaf_diag(self, d):
+        import torch
+        G = torch.empty_like(d)
+        dyson_leaf_diag(self.plan, int(d.shape[0]), _ptr(self._c(d)), _ptr(G), _stream())
+        return G
+
+    def xmatvec(self, level, d, q):
+        import torch
+        u = torch.empty_like(q)
+        dyson_xmatvec(self.plan, level, int(d.shape[0]), _ptr(self._c(d)), _ptr(self._c(q)),
+                      _ptr(u), _stream())
+        return u
+
+    def correct_level(self, level, d, Gacc):
+        import numpy as np
+        K = int(d.shape[0])
+        steps = np.zeros(K * self.info.n_nodes[level], np.int32)
+        dyson_correct_level(self.plan, level, K, _ptr(self._c(d)), _ptr(self._c(Gacc)), steps,
+                            _stream())
+        return steps.reshape(K, self.info.n_nodes[level])

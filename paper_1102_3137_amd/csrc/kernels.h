@@ -1,0 +1,104 @@
+// Device-side argument blocks and kernel launchers (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dyson {
+
+// Read-only geometry of a plan on the device (tile-major layout).
+struct TileGeom {
+  int T, S, sx, sy, N;
+  double t;
+  const int* nbr;        // [T*4]
+  const uint8_t* kind;   // [T*S] 0 pad, 1 leaf, 2 separator
+  const uint8_t* depth;  // [T*S]
+  const int* site_of;    // [T*S] natural index or -1
+  const int* pos_of;     // [N]
+};
+
+// Per-item scalars of the inner COCG solves (item = k * n_nodes + node).
+struct CocgState {
+  int* done;       // 0 open, 1 converged/skipped, 2 bilinear breakdown
+  int* iters;
+  double* rho;     // complex
+  double* alpha;   // complex
+  double* beta;    // complex
+  double* bn2;     // real
+};
+
+struct CocgLaunch {
+  TileGeom G;
+  int K;
+  int g;                 // graph level: sites with depth >= g (and leaves) are active
+  const int* tile_node;  // [T] domain of the tile at the Lanczos level
+  int n_nodes;
+  const int* item_skip;  // Lanczos "stopped" flags or null
+  CocgState st;
+  const double* d;
+  double *x, *r, *z, *p_old, *p_new, *s;
+  double* partial;       // [K*T*2] complex
+  const void* fac;       // tile factors for graph g
+  bool fp32;             // factors stored as complex64
+  unsigned long long* wctr;  // profiling: algorithmic bytes per kernel class, or null
+};
+
+struct LzArgs {
+  TileGeom G;
+  int level;
+  const int* tile_node;
+  int n_nodes;
+  uint64_t seed;
+  const uint64_t* fkey;  // [K] identity of frequency k (bits of w_k), keys the start vectors
+  int* stopped;     // 0 open, 1 exhausted, 2 step cap, 3 breakdown
+  int* restart;     // 1 while a restart vector is being built
+  int* nrestart;
+  int* steps;
+  double* alpha;    // complex
+  double* beta;     // complex: beta_j coupling q_{j-1}, q_j
+  double* unorm2;
+  double* scal;     // complex
+  double* partial;  // [K*T*2] complex
+  double* hpart;    // [K*T*hstride] complex
+  double* h;        // [K*n_nodes*hstride] complex
+  int hstride;
+  unsigned long long* wctr;  // profiling: algorithmic bytes per kernel class, or null
+};
+
+void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
+                    hipStream_t s);
+void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat, hipStream_t s);
+void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const double* omega,
+                     const double* sigma, double* d, hipStream_t s);
+void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
+                   void* fac, bool fp32, double* gdiag, hipStream_t s);
+
+void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s);
+void launch_cocg_stencil(const CocgLaunch& L, hipStream_t s);
+void launch_cocg_update(const CocgLaunch& L, hipStream_t s);
+void launch_cocg_scalars(const CocgLaunch& L, const int* tlo, const int* thi, int op, double tol2,
+                         int it, hipStream_t s);
+void launch_count_open(const int* done, int n, int* out, hipStream_t s);
+
+void launch_freq_keys(const double* omega, int K, uint64_t* fkey, hipStream_t s);
+void launch_lz_random(const LzArgs& a, int K, double* q, int only_flag, uint64_t salt,
+                      hipStream_t s);
+void launch_lz_scale(const LzArgs& a, int K, const double* src, double* dst, int only_flag,
+                     hipStream_t s);
+void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,
+                      hipStream_t s);
+void launch_lz_alpha(const LzArgs& a, int K, const double* q, const double* u, hipStream_t s);
+void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qprev, const double* u,
+                     double* r, double* gacc, hipStream_t s);
+void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
+                    const double* r, int only_flag, hipStream_t s);
+void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
+                       int only_flag, hipStream_t s);
+void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
+                       int only_flag, hipStream_t s);
+void launch_lz_norms(const LzArgs& a, int K, const double* r, int only_flag, hipStream_t s);
+void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s);
+void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
+                       int op, int j, double tol, double brk, int max_restarts, hipStream_t s);
+
+}  // namespace dyson

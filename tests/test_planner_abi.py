@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI library (no GPU needed): every symbol the
+header declares is exported, and the planner's partition matches the
+oracle's independent partition of the same lattice."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1102_3137_amd import binding as B
+from oracle import lowrank as olr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "dyson.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dyson_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    names = _declared_symbols()
+    assert "dyson_solve" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in B.SIGNATURES}
+    assert set(names) == bound
+
+
+def _host_plan(dims, s, part, **kw):
+    lat = B.Lattice()
+    lat.dim = len(dims)
+    for a in range(3):
+        lat.L[a] = dims[a] if a < len(dims) else 1
+    lat.t, lat.mu = -1.0, 0.5
+    o = B.Opts(s, part, kw.get("precision", 0), kw.get("max_rank", 0), 10, 2000, 1e-13, 1e-10,
+               1, 0)
+    return B.dyson_plan_create(None, lat, o)
+
+
+def _oracle_maps(dims, s, part):
+    nodes = olr.plan_boxes(dims, s, "single" if part == B.PART_SINGLE else "nested")
+    n = int(np.prod(dims))
+    depth = np.full(n, -1)
+    is_sep = np.zeros(n, int)
+    for nd in sorted(nodes, key=lambda q: q["level"]):
+        idx = olr._box_sites(dims, nd["box"])
+        if not nd["splits"]:
+            free = depth[idx] < 0
+            depth[idx[free]] = nd["level"]
+            continue
+        on = olr._interface_mask(dims, nd["box"], nd["splits"])
+        for i in idx[on]:
+            if depth[i] < 0:
+                depth[i] = nd["level"]
+                is_sep[i] = 1
+    per_level = {}
+    for nd in nodes:
+        if nd["splits"]:
+            on = olr._interface_mask(dims, nd["box"], nd["splits"])
+            per_level.setdefault(nd["level"], []).append(int(on.sum()))
+    return depth, is_sep, per_level
+
+
+CASES = [((32, 32), 16, B.PART_SINGLE), ((32, 32), 16, B.PART_NESTED), ((5, 5), 3, B.PART_SINGLE),
+         ((37, 29), 8, B.PART_NESTED), ((37, 29), 5, B.PART_SINGLE), ((40,), 8, B.PART_NESTED),
+         ((16, 16), 16, B.PART_NESTED), ((17, 3), 16, B.PART_NESTED), ((64, 48), 16, B.PART_NESTED),
+         ((256, 256), 16, B.PART_NESTED)]
+
+
+@pytest.mark.parametrize("dims,s,part", CASES)
+def test_planner_matches_oracle_partition(dims, s, part):
+    plan = _host_plan(dims, s, part)
+    try:
+        n = int(np.prod(dims))
+        depth, is_sep, tile = B.dyson_plan_get_maps(plan, n)
+        odepth, osep, per_level = _oracle_maps(dims, s, part)
+        assert np.array_equal(is_sep, osep)
+        assert np.array_equal(depth, odepth)
+        info = B.dyson_plan_get_info(plan)
+        assert info.levels == len(per_level)
+        for l, ms in per_level.items():
+            assert info.n_nodes[l] == len(ms)
+            assert info.max_m[l] == max(ms)
+            assert info.sum_m[l] == sum(ms)
+        # every tile holds exactly one leaf (subdomain)
+        leaf_tiles = tile[is_sep == 0]
+        assert len(np.unique(leaf_tiles)) == info.n_tiles
+    finally:
+        B.dyson_plan_destroy(plan)
+
+
+def test_nested_256_level_ranks():
+    """Recursive bisection of 256^2 with 16-site tiles: eight levels whose
+    largest interfaces are 256, 128, 128, 64, 64, 32, 32, 16 sites."""
+    plan = _host_plan((256, 256), 16, B.PART_NESTED)
+    info = B.dyson_plan_get_info(plan)
+    B.dyson_plan_destroy(plan)
+    assert info.levels == 8
+    assert [info.max_m[l] for l in range(8)] == [256, 128, 128, 64, 64, 32, 32, 16]
+
+
+def test_fig1_single_level():
+    plan = _host_plan((5, 5), 3, B.PART_SINGLE)
+    info = B.dyson_plan_get_info(plan)
+    B.dyson_plan_destroy(plan)
+    assert info.levels == 1 and info.n_nodes[0] == 1 and info.max_m[0] == 9 and info.n_tiles == 4
+
+
+@pytest.mark.parametrize("dims,s", [((4, 4, 4), 4), ((8, 8), 1), ((8, 8), 17), ((0, 8), 4)])
+def test_planner_rejects_invalid(dims, s):
+    with pytest.raises(B.DysonError) as e:
+        _host_plan(dims, s, B.PART_NESTED)
+    assert e.value.status == 1
