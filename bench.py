@@ -1,0 +1,197 @@
+"""Throughput benchmark: G_ii site-frequencies per second on one MI355X.
+
+Workload: 256x256 open square lattice (N = 65536), t = -1, mu = 0.5,
+V_i = 2e-4 r_i^2, Sigma_i(i w) = a_i/(i w + b_i) seeded, 64 Matsubara
+frequencies at beta = 20, 16x16 subdomain tiles, recursive bisection,
+Lanczos to full interface rank (truncated ranks do not reach 1e-6).
+One step = one dyson_solve over all 64 frequencies: assembly, subdomain
+factorization and diag(B^{-1}), eight correction levels of bilinear Lanczos
+with inner solves, combine and scatter.  Inputs are resident in HBM before
+the timed region.
+
+Prints one JSON line.  Diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+KERNEL_NAMES = ["k_cocg_update", "k_cocg_stencil", "k_cgs_update", "k_cgs_dot"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["kernels.hip", "kernels.h"]:
+        h.update(open(os.path.join(ROOT, "paper_1102_3137_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        tab = json.load(open(path))
+    except Exception:
+        return None
+    ent = tab.get(f"{kernel}|{workload}|{precision}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, n_freq_sample, max_seconds=30.0):
+    """The oracle (block-tridiagonal recursive Green's function, FP64) timed on
+    the host on a bounded sample of the same workload's frequencies."""
+    import numpy as np
+
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    V, om, sig = synth.make_inputs(w)
+    d = oracle.assemble_diag(V, om, sig, w.mu)
+    done = 0
+    t0 = time.perf_counter()
+    results = {}
+    for k in range(min(n_freq_sample, w.n_freq)):
+        results[k] = oracle.diag_inv_rgf(w.dims, d[k], w.t)
+        done += 1
+        if time.perf_counter() - t0 > max_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=w.n_sites * done / dt, unit="site*freq/s", cores=threads, kind="oracle",
+                sample=f"{done} of {w.n_freq} frequencies of the same {w.dims[0]}x{w.dims[1]} "
+                       f"lattice, O2 recursive Green's function, FP64, {dt:.1f} s"), results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", choices=["square256", "square128", "small32"], default="square256")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not time the hot kernels with HIP events")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
+    ap.add_argument("--cpu-freqs", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1102_3137_amd import Plan, PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED
+
+    if args.workload == "square256":
+        w, s, part = synth.SQUARE_256, 16, PART_NESTED
+    elif args.workload == "square128":
+        w, s, part = synth.scaled_square(128, 64), 16, PART_NESTED
+    else:
+        w, s, part = synth.SMALL_32, 16, PART_SINGLE
+    prec = PREC_MIXED if args.precision == "mixed" else PREC_FP64
+    dev = torch.device("cuda:0")
+    V, om, sig = synth.make_inputs(w)
+    tV = torch.from_numpy(V).to(dev)
+    tom = torch.from_numpy(om).to(dev)
+    tsig = torch.from_numpy(np.ascontiguousarray(sig)).to(dev)
+    G = torch.empty((w.n_freq, w.n_sites), dtype=torch.complex128, device=dev)
+    plan = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
+                profile=not args.no_profile)
+    log(f"plan: {w.name}, levels={plan.info.levels}, "
+        f"max m per level={[plan.info.max_m[l] for l in range(plan.info.levels)]}, "
+        f"footprint={plan.footprint(w.n_freq) / 2**30:.2f} GiB")
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        plan.solve(tV, tom, tsig, G)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.3f} s")
+
+    lat, reports = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        _, rep = plan.solve(tV, tom, tsig, G, report=True)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        reports.append(rep)
+        log(f"step {i}: {lat[-1]:.3f} s  inner_iters_max={rep['inner_iters_max']} "
+            f"lanczos_steps={rep['lanczos_steps']} restarts={rep['restarts']}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = 1000.0 * t_total / args.steps
+    work = w.n_sites * w.n_freq
+
+    # roofline of the dominant kernel: algorithmic bytes / event-timed duration
+    roof = None
+    if not args.no_profile:
+        tot_ms = [sum(r["kern_ms"][c] for r in reports) for c in range(4)]
+        tot_b = [sum(r["kern_bytes"][c] for r in reports) for c in range(4)]
+        tot_n = [sum(r["kern_launches"][c] for r in reports) for c in range(4)]
+        c = int(np.argmax(tot_ms))
+        achieved = tot_b[c] / (tot_ms[c] * 1e-3) / 1e9 if tot_ms[c] > 0 else 0.0
+        tr = traffic_for(KERNEL_NAMES[c], args.workload, args.precision)
+        roof = {"bound": "hbm", "kernel": KERNEL_NAMES[c], "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": tr, "avg_launch_us": round(1000.0 * tot_ms[c] / max(tot_n[c], 1), 2),
+                "launches": tot_n[c], "algorithmic_bytes_per_launch": tot_b[c] / max(tot_n[c], 1),
+                "kernel_ms_share": {KERNEL_NAMES[i]: round(tot_ms[i] / args.steps, 1)
+                                    for i in range(4)}}
+
+    # accuracy against the oracle on a sample of frequencies (outside the timed region)
+    cpu, err, value = None, None, work / (ms_per_step / 1000.0)
+    if not args.no_cpu:
+        cpu, ref = cpu_baseline(w, args.cpu_freqs)
+        Gh = G.cpu().numpy()
+        import oracle
+        err = max(oracle.rel_err(Gh[k], ref[k]) for k in ref)
+        log(f"max rel err on {len(ref)} sampled frequencies: {err:.3e}")
+        if not err <= 1e-6:
+            value = 0.0   # only results within 1e-6 of the oracle count
+
+    lat_sorted = sorted(lat)
+    out = {
+        "metric": "G_ii sites*freqs/sec at rel err <= 1e-6 vs FP64 oracle; p50/p99 solve latency",
+        "value": value, "unit": "site*freq/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 preconditioner + f64" if prec == PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + (", 16x16 subdomains, recursive bisection, full rank"
+                                         if part == PART_NESTED else ", 4 subdomains, full rank"),
+                   "lattice": list(w.dims), "n_freq": w.n_freq, "beta": w.beta,
+                   "precision": args.precision, "parallelism": "1 GPU"},
+        "latency_s": {"p50": lat_sorted[len(lat) // 2],
+                      "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
+        "max_rel_err_sampled": err,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,8 +88,10 @@ typedef struct {
   int inner_iters_max;      /* worst single inner solve */
   int restarts;             /* breakdown restarts */
   int truncated;            /* 1 if any domain stopped at max_rank before exhaustion */
-  /* per-kernel-class timing (profile=1): 0 = inner-solve update/preconditioner,
-   * 1 = inner-solve stencil, 2 = re-orthogonalization, 3 = other */
+  /* per-kernel timing (profile=1), HIP events on the call's stream:
+   * 0 = inner-solve update + tile preconditioner (k_cocg_update),
+   * 1 = inner-solve stencil (k_cocg_stencil), 2 = re-orthogonalization
+   * update (k_cgs_update), 3 = re-orthogonalization products (k_cgs_dot) */
   double kern_ms[4];
   long long kern_launches[4];
   double kern_bytes[4];     /* algorithmic HBM bytes those launches moved */

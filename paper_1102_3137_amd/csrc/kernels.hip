@@ -729,7 +729,7 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   const size_t base = (size_t)k * NP + (size_t)t * G.S;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[2], (unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
+    atomicAdd(&a.wctr[3], (unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
   cd rl[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {

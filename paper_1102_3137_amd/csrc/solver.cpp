@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -282,7 +283,7 @@ struct Run {
     c.wctr = p->prof.on ? p->d_prof : nullptr;
     const double tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
     const int n_items = K * L.n;
-    timed(0, [&] { launch_cocg_init(c, b, s); });
+    launch_cocg_init(c, b, s);
     launch_cocg_scalars(c, L.tlo, L.thi, 0, tol2, 0, s);
     int it = 0, open = n_items;
     for (it = 0; it < HP.opts.max_inner_iters; ++it) {
@@ -360,7 +361,7 @@ struct Run {
   void cgs2(const LzArgs& a, const DevLevel& L, int nvec, int only_flag) {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
-      timed(2, [&] { launch_cgs_dot(a, K, p->Q, qstride, nvec, p->R, only_flag, s); });
+      timed(3, [&] { launch_cgs_dot(a, K, p->Q, qstride, nvec, p->R, only_flag, s); });
       launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, only_flag, s);
       timed(2, [&] { launch_cgs_update(a, K, p->Q, qstride, nvec, p->R, only_flag, s); });
     }
@@ -712,10 +713,20 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
   // a5-a9: corrections bottom-up
   int max_rank_used = 0;
   long long lsteps = 0;
+  const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
   for (int l = (int)P.levels.size() - 1; l >= 0; --l) {
     std::vector<int> steps;
+    auto tl = std::chrono::steady_clock::now();
     CHECKED(run.lanczos_level(l, &steps));
-    for (int v : steps) max_rank_used = std::max(max_rank_used, v), lsteps += v;
+    int lmax = 0;
+    for (int v : steps) max_rank_used = std::max(max_rank_used, v), lsteps += v, lmax = std::max(lmax, v);
+    if (verbose) {
+      std::fprintf(stderr, "[dyson] level %d: %d domains x %d freqs, max steps %d, %.1f ms, inner iters so far %lld\n",
+                   l, p->lv[l].n, K, lmax,
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count(),
+                   p->stat_inner);
+      std::fflush(stderr);
+    }
     if (p->pending != DYSON_OK) break;
   }
   // a8: scatter to natural order
