@@ -93,7 +93,19 @@ def main():
                     help="do not time the hot kernels with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 8,
+                          "calibrate_copy_bytes_written": y.numel() * 8, "launches": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
