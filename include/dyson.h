@@ -70,10 +70,11 @@ typedef struct {
                          subdomain factors in the inner preconditioner, FP64
                          residuals and FP64 Lanczos [FP64] */
   int max_rank;       /* cap on Lanczos steps per domain (truncated rank); 0 = full [0] */
-  int extra_steps;    /* steps allowed beyond the interface size m (Sec. II.C) [10] */
+  int extra_steps;    /* steps allowed beyond the interface size m (Sec. II.C):
+                         the cap is m + max(extra_steps, ceil(m/8)) [10] */
   int max_inner_iters;/* iteration cap of each inner solve [2000] */
-  double inner_tol;   /* relative residual of the inner solves [1e-13] */
-  double lanczos_tol; /* stop when |r|_2 <= lanczos_tol*|u|_2 [1e-10] */
+  double inner_tol;   /* relative residual of the inner solves [1e-14] */
+  double lanczos_tol; /* stop when |r|_2 <= lanczos_tol*|u|_2 [1e-11] */
   uint64_t seed;      /* seed of the Lanczos start vectors [0x5eed] */
   int profile;        /* 1: time the hot kernels with HIP events into the report */
 } dyson_opts;
@@ -87,7 +88,9 @@ typedef struct {
   long long inner_iters;    /* sum over inner solves and items of iterations */
   int inner_iters_max;      /* worst single inner solve */
   int restarts;             /* breakdown restarts */
-  int truncated;            /* 1 if any domain stopped at max_rank before exhaustion */
+  int truncated;            /* 1 if any (domain, frequency) stopped at its step cap
+                               (max_rank or m + extra) before the Krylov space of X
+                               was exhausted: that result is not full rank */
   /* per-kernel timing (profile=1), HIP events on the call's stream:
    * 0 = inner-solve update + tile preconditioner (k_cocg_update),
    * 1 = inner-solve stencil (k_cocg_stencil), 2 = re-orthogonalization

@@ -188,7 +188,7 @@ class Plan:
 
     def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
-                 inner_tol=1e-13, lanczos_tol=1e-10, seed=0x5EED, profile=False, device=0):
+                 inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)

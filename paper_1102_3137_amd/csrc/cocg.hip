@@ -1,0 +1,421 @@
+// Inner solves of the X-matvec (eqs. (10)-(11)): preconditioned COCG, the
+// conjugate-gradient variant for complex-symmetric matrices in which every
+// inner product is the bilinear form of Sec. II.A (no conjugation).
+//
+// A_g is the lattice restricted to the sites active in graph g; M is the
+// block diagonal of A_g over tiles (a tile = one leaf subdomain plus its
+// high-side separator fringe), factored by k_factor as a block LDL^T over
+// the tile's rows of sx sites.
+//
+// Work unit = one (tile, frequency) handled by ONE wavefront; four units
+// per workgroup.  Nothing synchronises across waves: the tile solve passes
+// its row vectors through the wave's own LDS slice.  No data crosses
+// workgroups inside a launch (the eight XCDs keep separate L2 caches): each
+// unit writes its partial sums, and the NEXT launch's waves re-reduce the
+// partials of their item in a fixed order (so every wave derives the same
+// scalars, deterministically); the wave on the item's first tile records
+// the item state.  An iteration is two launches (stencil, update); the host
+// polls convergence through a one-workgroup check kernel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace dyson {
+namespace {
+using namespace dev;
+
+constexpr int WAVES = 4;  // units per workgroup
+
+struct Unit {
+  int k, t, node, item, lane, wave;
+  bool ok;
+};
+
+__device__ __forceinline__ Unit decode(const CocgLaunch& a) {
+  Unit u;
+  u.wave = threadIdx.x >> 6;
+  u.lane = threadIdx.x & 63;
+  const int id = blockIdx.x * WAVES + u.wave;
+  u.ok = id < a.K * a.G.T;
+  u.k = u.ok ? id / a.G.T : 0;
+  u.t = u.ok ? id % a.G.T : 0;
+  u.node = u.ok ? a.tile_node[u.t] : -1;
+  u.item = u.k * a.n_nodes + u.node;
+  u.ok = u.ok && u.node >= 0;
+  return u;
+}
+
+// Sum over the item's tiles of `per` complex partials per unit, fixed order.
+__device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
+                                         const Unit& u, cd& s0, cd& s1) {
+  const int lo = a.tlo[u.node], hi = a.thi[u.node];
+  s0 = cmk(0.0, 0.0);
+  s1 = cmk(0.0, 0.0);
+  for (int tt = lo + u.lane; tt < hi; tt += 64) {
+    const size_t qq = ((size_t)u.k * a.G.T + tt) * per;
+    s0 = cadd(s0, ld(part, qq));
+    if (per == 2) s1 = cadd(s1, ld(part, qq + 1));
+  }
+  s0 = wave_sum(s0);
+  if (per == 2) s1 = wave_sum(s1);
+}
+
+// ---------------------------------------------------------- tile solve
+// Lane L owns row i = L>>2 and columns 4c..4c+3 (c = L&3) of every slice
+// inverse S_y^{-1}.  complex64 factors stay in registers (64 complex per
+// lane, loaded once); FP64 factors are streamed per slice in both sweeps.
+// Arithmetic is FP64 either way.
+template <typename F, bool REG>
+struct WaveFactor;
+
+// complex64 factors held in registers for the whole solve (raw bits, so the
+// compiler keeps 64 complex64 values = 128 VGPRs instead of widening them)
+template <>
+struct WaveFactor<float, true> {
+  uint32_t gr[16][4], gi[16][4];
+  __device__ __forceinline__ void load(const float* fac, size_t fbase, int sx, int sy, int lane) {
+    const int i = lane >> 2, c = lane & 3;
+#pragma unroll
+    for (int y = 0; y < 16; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * c + e;
+        float2 v = (y < sy && i < sx && j < sx)
+                       ? reinterpret_cast<const float2*>(fac)[fbase + (size_t)y * sx * sx + i * sx + j]
+                       : make_float2(0.f, 0.f);
+        gr[y][e] = __float_as_uint(v.x);
+        gi[y][e] = __float_as_uint(v.y);
+      }
+  }
+  __device__ __forceinline__ cd get(int y, int e, const float*, size_t, int, int) const {
+    uint32_t a = gr[y][e], b = gi[y][e];
+    asm volatile("" : "+v"(a), "+v"(b));
+    return cmk((double)__uint_as_float(a), (double)__uint_as_float(b));
+  }
+};
+
+// factors streamed from memory slice by slice (read in both sweeps)
+template <typename F>
+struct WaveFactor<F, false> {
+  __device__ __forceinline__ void load(const F*, size_t, int, int, int) {}
+  __device__ __forceinline__ cd get(int y, int e, const F* fac, size_t fbase, int sx,
+                                    int lane) const {
+    const int i = lane >> 2, j = 4 * (lane & 3) + e;
+    return (i < sx && j < sx) ? ldf<F>(fac, fbase + (size_t)y * sx * sx + i * sx + j)
+                              : cmk(0.0, 0.0);
+  }
+};
+
+// In place: zl holds r on entry and z = M^{-1} r on exit (tile-local index
+// l = x + sx*y).  Block forward z_y = r_y - T_y S_{y-1}^{-1} z_{y-1}, block
+// backward v_y = S_y^{-1}(z_y - T_{y+1} v_{y+1}), T_y = t diag(active bonds).
+template <typename F, bool REG>
+__device__ __forceinline__ void wave_tile_solve(const WaveFactor<F, REG>& f, const F* fac, size_t fbase,
+                                                cd* zl, const uint8_t* act, int sx, int sy,
+                                                double tt, int lane) {
+  const int i = lane >> 2, c = lane & 3;
+  wave_sync();
+#pragma unroll
+  for (int y = 1; y < 16; ++y) {
+    if (y < sy) {
+      cd acc = cmk(0.0, 0.0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * c + e;
+        if (j < sx) acc = cfma(f.get(y - 1, e, fac, fbase, sx, lane), zl[j + sx * (y - 1)], acc);
+      }
+      acc = quad_sum(acc);
+      if (c == 0 && i < sx) {
+        const int l = i + sx * y;
+        if (act[l] && act[l - sx]) zl[l] = csub(zl[l], cscale(acc, tt));
+      }
+      wave_sync();
+    }
+  }
+#pragma unroll
+  for (int y = 15; y >= 0; --y) {
+    if (y < sy) {
+      cd acc = cmk(0.0, 0.0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * c + e;
+        if (j < sx) {
+          const int l = j + sx * y;
+          cd row = zl[l];
+          if (y < sy - 1 && act[l] && act[l + sx]) row = csub(row, cscale(zl[l + sx], tt));
+          acc = cfma(f.get(y, e, fac, fbase, sx, lane), row, acc);
+        }
+      }
+      acc = quad_sum(acc);
+      wave_sync();
+      if (c == 0 && i < sx) zl[i + sx * y] = acc;
+      wave_sync();
+    }
+  }
+}
+
+// ------------------------------------------------------------- kernels
+// r = b (masked to graph g), x = 0, p = 0, z = M^{-1} r;
+// item totals: rho = r^T z, bn2 = |b|^2
+template <typename F, bool REG>
+__global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* __restrict__ b) {
+  const Unit u = decode(a);
+  if (!u.ok) return;
+  if (a.item_skip && a.item_skip[u.item]) return;
+  const TileGeom& G = a.G;
+  __shared__ cd zsh[WAVES][256];
+  __shared__ uint8_t ash[WAVES][256];
+  cd* zl = zsh[u.wave];
+  uint8_t* act = ash[u.wave];
+  const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  cd rv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    rv[e] = cmk(0.0, 0.0);
+    uint8_t ac = 0;
+    if (l < G.S) {
+      const size_t p = (size_t)u.t * G.S + l;
+      ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
+      if (ac) rv[e] = ld(b, base + l);
+    }
+    act[l] = ac;
+    zl[l] = rv[e];
+  }
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  WaveFactor<F, REG> f;
+  f.load(fac, fbase, G.sx, G.sy, u.lane);
+  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, u.lane);
+  cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    if (l < G.S) {
+      const cd zv = act[l] ? zl[l] : cmk(0.0, 0.0);
+      st(a.r, base + l, rv[e]);
+      st(a.z, base + l, zv);
+      st(a.x, base + l, cmk(0.0, 0.0));
+      st(a.p_old, base + l, cmk(0.0, 0.0));
+      rz = cfma(rv[e], zv, rz);
+      rr.x += cabs2(rv[e]);
+    }
+  }
+  rz = wave_sum(rz);
+  rr = wave_sum(rr);
+  if (u.lane == 0) {
+    const size_t q = ((size_t)u.k * G.T + u.t) * 2;
+    st(a.partU, q, rz);
+    st(a.partU, q + 1, rr);
+  }
+}
+
+// Convergence test of the previous update, beta = rho_i / rho_{i-1};
+// p_new = z + beta p_old ; s = A_g p_new ; partial mu = p^T s
+__global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
+  const Unit u = decode(a);
+  if (!u.ok || a.st.done[u.item]) return;
+  const TileGeom& G = a.G;
+  const size_t NP = (size_t)G.T * G.S;
+  const size_t kb = (size_t)u.k * NP;
+  const size_t base = kb + (size_t)u.t * G.S;
+  const bool lead = u.t == a.tlo[u.node];  // records the item state
+  cd beta = cmk(0.0, 0.0);
+  if (it > 0) {
+    cd rho, rr;
+    item_sum(a.partU, 2, a, u, rho, rr);
+    if (rr.x <= a.tol2 * a.st.bn2[u.item]) {
+      if (lead && u.lane == 0) {
+        a.st.done[u.item] = 1;
+        a.st.iters[u.item] = it;
+      }
+      return;
+    }
+    beta = cdiv(rho, ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item));
+    if (lead && u.lane == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
+  }
+  if (a.wctr && u.lane == 0)
+    atomicAdd(&a.wctr[1], (unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
+  __shared__ cd psh[WAVES][256];
+  cd* pl = psh[u.wave];
+  const int sx = G.sx;
+  bool ac[4];
+  cd pn[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    ac[e] = false;
+    pn[e] = cmk(0.0, 0.0);
+    if (l < G.S) {
+      const size_t p = (size_t)u.t * G.S + l;
+      ac[e] = active(G.kind[p], G.depth[p], a.g);
+      if (ac[e]) pn[e] = cfma(beta, ld(a.p_old, base + l), ld(a.z, base + l));
+      st(a.p_new, base + l, pn[e]);
+    }
+    pl[l] = pn[e];
+  }
+  wave_sync();
+  cd mu = cmk(0.0, 0.0);
+  // value of p_new at a site of a neighbouring tile (same domain when active)
+  auto halo = [&](int nt, int nl) -> cd {
+    const size_t np = (size_t)nt * G.S + nl;
+    if (!active(G.kind[np], G.depth[np], a.g)) return cmk(0.0, 0.0);
+    return cfma(beta, ld(a.p_old, kb + np), ld(a.z, kb + np));
+  };
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    if (l >= G.S) continue;
+    if (!ac[e]) {
+      st(a.s, base + l, cmk(0.0, 0.0));
+      continue;
+    }
+    const int lx = l % sx, ly = l / sx;
+    cd nb = cmk(0.0, 0.0);
+    if (lx > 0) nb = cadd(nb, pl[l - 1]);
+    else if (G.nbr[u.t * 4 + 0] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 0], l + sx - 1));
+    if (lx < sx - 1) nb = cadd(nb, pl[l + 1]);
+    else if (G.nbr[u.t * 4 + 1] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 1], l - (sx - 1)));
+    if (G.sy > 1) {
+      if (ly > 0) nb = cadd(nb, pl[l - sx]);
+      else if (G.nbr[u.t * 4 + 2] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 2], l + sx * (G.sy - 1)));
+      if (ly < G.sy - 1) nb = cadd(nb, pl[l + sx]);
+      else if (G.nbr[u.t * 4 + 3] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 3], l - sx * (G.sy - 1)));
+    }
+    const cd sv = cfma(ld(a.d, base + l), pn[e], cscale(nb, G.t));
+    st(a.s, base + l, sv);
+    mu = cfma(pn[e], sv, mu);
+  }
+  mu = wave_sum(mu);
+  if (u.lane == 0) st(a.partS, (size_t)u.k * G.T + u.t, mu);
+}
+
+// x += alpha p ; r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z,
+// |r|^2 ; converged when |r|^2 <= tol^2 |b|^2, else beta = rho'/rho
+template <typename F, bool REG>
+__global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
+  const Unit u = decode(a);
+  if (!u.ok || a.st.done[u.item]) return;
+  const TileGeom& G = a.G;
+  const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  cd mu, unused;
+  item_sum(a.partS, 1, a, u, mu, unused);
+  if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
+    if (u.t == a.tlo[u.node] && u.lane == 0) a.st.done[u.item] = 2;
+    return;
+  }
+  const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
+  if (a.wctr && u.lane == 0)
+    atomicAdd(&a.wctr[0], (unsigned long long)(G.S * (7 * 16 + 2)) +
+                              (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  __shared__ cd zsh[WAVES][256];
+  __shared__ cd rsh[WAVES][256];
+  __shared__ uint8_t ash[WAVES][256];
+  cd* zl = zsh[u.wave];
+  cd* rl = rsh[u.wave];
+  uint8_t* act = ash[u.wave];
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  WaveFactor<F, REG> f;
+  f.load(fac, fbase, G.sx, G.sy, u.lane);  // issued early: overlaps the vector traffic
+  cd rr = cmk(0.0, 0.0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    cd rv = cmk(0.0, 0.0);
+    uint8_t ac = 0;
+    if (l < G.S) {
+      const size_t p = (size_t)u.t * G.S + l;
+      ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
+      if (ac) {
+        const cd pv = ld(a.p_new, base + l);
+        st(a.x, base + l, cfma(alpha, pv, ld(a.x, base + l)));
+        rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
+      }
+      st(a.r, base + l, rv);
+      rr.x += cabs2(rv);
+    }
+    act[l] = ac;
+    zl[l] = rv;
+    rl[l] = rv;
+  }
+  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, u.lane);
+  cd rz = cmk(0.0, 0.0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    if (l < G.S) {
+      const cd zv = act[l] ? zl[l] : cmk(0.0, 0.0);
+      st(a.z, base + l, zv);
+      rz = cfma(rl[l], zv, rz);
+    }
+  }
+  rz = wave_sum(rz);
+  rr = wave_sum(rr);
+  if (u.lane == 0) {
+    const size_t q = ((size_t)u.k * G.T + u.t) * 2;
+    st(a.partU, q, rz);
+    st(a.partU, q + 1, rr);
+  }
+}
+
+// One workgroup: convergence bookkeeping after launch `it` (it = 0 follows
+// the initialisation) and the number of items still open.
+__global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* __restrict__ open) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int item = threadIdx.x; item < a.n_items; item += blockDim.x) {
+    const int k = item / a.n_nodes, node = item % a.n_nodes;
+    if (a.item_skip && a.item_skip[item]) {
+      a.st.done[item] = 1;
+      continue;
+    }
+    if (it > 0 && a.st.done[item]) continue;
+    cd s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+    for (int t = a.tlo[node]; t < a.thi[node]; ++t) {
+      const size_t q = ((size_t)k * a.G.T + t) * 2;
+      s0 = cadd(s0, ld(a.partU, q));
+      s1 = cadd(s1, ld(a.partU, q + 1));
+    }
+    if (it == 0) {
+      a.st.bn2[item] = s1.x;
+      st(a.rho2, item, s0);
+      a.st.iters[item] = 0;
+      a.st.done[item] = (s1.x > 0.0) ? 0 : 1;
+    } else if (s1.x <= a.tol2 * a.st.bn2[item]) {
+      a.st.done[item] = 1;
+      a.st.iters[item] = it;
+    }
+    mine += a.st.done[item] == 0;
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *open = cnt;
+}
+
+}  // namespace
+
+static inline unsigned cocg_blocks(const CocgLaunch& L) {
+  return (unsigned)(((size_t)L.K * L.G.T + WAVES - 1) / WAVES);
+}
+
+void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
+  if (L.fp32) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  else k_cocg_init<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+}
+void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s) {
+  k_cocg_stencil<<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+}
+void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
+  k_cocg_check<<<1, 256, 0, s>>>(L, it, open);
+}
+void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
+  if (L.fp32) k_cocg_update<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  else k_cocg_update<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+}
+
+}  // namespace dyson

@@ -1,0 +1,132 @@
+// Device helpers shared by the HIP sources: complex FP64 arithmetic on
+// interleaved pairs, loads/stores, wave and block reductions, the
+// activity rule of a graph level and a counter-based random generator.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dyson {
+namespace dev {
+
+struct cd {
+  double x, y;
+};
+__device__ __forceinline__ cd cmk(double a, double b) { return cd{a, b}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
+__device__ __forceinline__ cd cfma(cd a, cd b, cd c) {  // a*b + c
+  return cd{fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+}
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+  double den = b.x * b.x + b.y * b.y;
+  return cd{(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
+}
+__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+// principal square root of a complex number
+__device__ __forceinline__ cd csqrt_p(cd a) {
+  double r = sqrt(sqrt(a.x * a.x + a.y * a.y));
+  double th = 0.5 * atan2(a.y, a.x);
+  return cd{r * cos(th), r * sin(th)};
+}
+
+__device__ __forceinline__ cd ld(const double* p, size_t i) {
+  const double2 v = reinterpret_cast<const double2*>(p)[i];
+  return cd{v.x, v.y};
+}
+__device__ __forceinline__ void st(double* p, size_t i, cd v) {
+  reinterpret_cast<double2*>(p)[i] = make_double2(v.x, v.y);
+}
+template <typename F>
+__device__ __forceinline__ cd ldf(const F* p, size_t i);
+template <>
+__device__ __forceinline__ cd ldf<double>(const double* p, size_t i) {
+  return ld(p, i);
+}
+template <>
+__device__ __forceinline__ cd ldf<float>(const float* p, size_t i) {
+  const float2 v = reinterpret_cast<const float2*>(p)[i];
+  return cd{(double)v.x, (double)v.y};
+}
+template <typename F>
+__device__ __forceinline__ void stf(F* p, size_t i, cd v);
+template <>
+__device__ __forceinline__ void stf<double>(double* p, size_t i, cd v) {
+  st(p, i, v);
+}
+template <>
+__device__ __forceinline__ void stf<float>(float* p, size_t i, cd v) {
+  reinterpret_cast<float2*>(p)[i] = make_float2((float)v.x, (float)v.y);
+}
+
+__device__ __forceinline__ bool active(uint8_t kind, uint8_t depth, int g) {
+  return kind == 1 || (kind == 2 && (int)depth >= g);
+}
+
+// wave64 sum of a complex value
+__device__ __forceinline__ cd wave_sum(cd v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+// sum over the 16-lane row group (lanes with equal tid>>4)
+__device__ __forceinline__ cd row16_sum(cd v) {
+  for (int o = 8; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 16);
+    v.y += __shfl_xor(v.y, o, 16);
+  }
+  return v;
+}
+// block (256 threads) sum of up to two complex values; result valid in thread 0
+__device__ __forceinline__ void block_sum2(cd& a, cd& b) {
+  __shared__ cd red[2][4];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = cadd(cadd(red[0][0], red[0][1]), cadd(red[0][2], red[0][3]));
+    b = cadd(cadd(red[1][0], red[1][1]), cadd(red[1][2], red[1][3]));
+  }
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): counter-based 64-bit mixer.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double u01(uint64_t z) {  // [0,1)
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+
+// wave-scope fence + barrier: orders LDS traffic between the lanes of one wave
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sum over the 4 lanes of a quad (lanes 4q..4q+3)
+__device__ __forceinline__ cd quad_sum(cd v) {
+  v.x += __shfl_xor(v.x, 1, 64);
+  v.y += __shfl_xor(v.y, 1, 64);
+  v.x += __shfl_xor(v.x, 2, 64);
+  v.y += __shfl_xor(v.y, 2, 64);
+  return v;
+}
+
+}  // namespace dev
+}  // namespace dyson

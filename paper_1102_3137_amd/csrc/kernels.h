@@ -21,10 +21,7 @@ struct TileGeom {
 struct CocgState {
   int* done;       // 0 open, 1 converged/skipped, 2 bilinear breakdown
   int* iters;
-  double* rho;     // complex
-  double* alpha;   // complex
-  double* beta;    // complex
-  double* bn2;     // real
+  double* bn2;     // |b|^2
 };
 
 struct CocgLaunch {
@@ -37,10 +34,16 @@ struct CocgLaunch {
   CocgState st;
   const double* d;
   double *x, *r, *z, *p_old, *p_new, *s;
-  double* partial;       // [K*T*2] complex
   const void* fac;       // tile factors for graph g
   bool fp32;             // factors stored as complex64
   unsigned long long* wctr;  // profiling: algorithmic bytes per kernel class, or null
+  const int* tlo;        // [n_nodes] tile range of each domain
+  const int* thi;
+  int n_items;           // K * n_nodes
+  double* partS;         // [K*T] complex: p^T A p per unit
+  double* partU;         // [K*T*2] complex: r^T z and |r|^2 per unit
+  double* rho2;          // [2][n_items] complex: r^T z of the last two iterations
+  double tol2;           // squared relative residual target
 };
 
 struct LzArgs {
@@ -50,13 +53,12 @@ struct LzArgs {
   int n_nodes;
   uint64_t seed;
   const uint64_t* fkey;  // [K] identity of frequency k (bits of w_k), keys the start vectors
-  int* stopped;     // 0 open, 1 exhausted, 2 step cap, 3 breakdown
-  int* restart;     // 1 while a restart vector is being built
-  int* nrestart;
+  int* stopped;     // 0 open, 1 exhausted, 2 step cap, 3 breakdown, 4 done earlier
   int* steps;
   double* alpha;    // complex
   double* beta;     // complex: beta_j coupling q_{j-1}, q_j
-  double* unorm2;
+  double* unorm2;   // |u|^2 of the current step
+  double* umax2;    // running max of |u|^2 over the item's steps
   double* scal;     // complex
   double* partial;  // [K*T*2] complex
   double* hpart;    // [K*T*hstride] complex
@@ -74,31 +76,30 @@ void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const 
                    void* fac, bool fp32, double* gdiag, hipStream_t s);
 
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s);
-void launch_cocg_stencil(const CocgLaunch& L, hipStream_t s);
-void launch_cocg_update(const CocgLaunch& L, hipStream_t s);
-void launch_cocg_scalars(const CocgLaunch& L, const int* tlo, const int* thi, int op, double tol2,
-                         int it, hipStream_t s);
+void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s);
+void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s);
+void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s);
 void launch_count_open(const int* done, int n, int* out, hipStream_t s);
 
 void launch_freq_keys(const double* omega, int K, uint64_t* fkey, hipStream_t s);
-void launch_lz_random(const LzArgs& a, int K, double* q, int only_flag, uint64_t salt,
-                      hipStream_t s);
-void launch_lz_scale(const LzArgs& a, int K, const double* src, double* dst, int only_flag,
-                     hipStream_t s);
+void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s);
+void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s);
 void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,
                       hipStream_t s);
 void launch_lz_alpha(const LzArgs& a, int K, const double* q, const double* u, hipStream_t s);
 void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qprev, const double* u,
-                     double* r, double* gacc, hipStream_t s);
+                     double* r, double* D, hipStream_t s);
 void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
-                    const double* r, int only_flag, hipStream_t s);
+                    const double* r, hipStream_t s);
 void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
-                       int only_flag, hipStream_t s);
+                       hipStream_t s);
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
-                       int only_flag, hipStream_t s);
-void launch_lz_norms(const LzArgs& a, int K, const double* r, int only_flag, hipStream_t s);
+                       double* D, hipStream_t s);
+void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s);
 void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s);
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
-                       int op, int j, double tol, double brk, int max_restarts, hipStream_t s);
+                       int op, int j, double tol, double brk, hipStream_t s);
+void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s);
+void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s);
 
 }  // namespace dyson

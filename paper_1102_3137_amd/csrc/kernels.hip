@@ -6,113 +6,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "devcommon.h"
 #include "kernels.h"
 
 namespace dyson {
 namespace {
-
-struct cd {
-  double x, y;
-};
-__device__ __forceinline__ cd cmk(double a, double b) { return cd{a, b}; }
-__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ cd cmul(cd a, cd b) {
-  return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-__device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
-__device__ __forceinline__ cd cfma(cd a, cd b, cd c) {  // a*b + c
-  return cd{fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
-}
-__device__ __forceinline__ cd cdiv(cd a, cd b) {
-  double den = b.x * b.x + b.y * b.y;
-  return cd{(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
-}
-__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
-// principal square root of a complex number
-__device__ __forceinline__ cd csqrt_p(cd a) {
-  double r = sqrt(sqrt(a.x * a.x + a.y * a.y));
-  double th = 0.5 * atan2(a.y, a.x);
-  return cd{r * cos(th), r * sin(th)};
-}
-
-__device__ __forceinline__ cd ld(const double* p, size_t i) {
-  const double2 v = reinterpret_cast<const double2*>(p)[i];
-  return cd{v.x, v.y};
-}
-__device__ __forceinline__ void st(double* p, size_t i, cd v) {
-  reinterpret_cast<double2*>(p)[i] = make_double2(v.x, v.y);
-}
-template <typename F>
-__device__ __forceinline__ cd ldf(const F* p, size_t i);
-template <>
-__device__ __forceinline__ cd ldf<double>(const double* p, size_t i) {
-  return ld(p, i);
-}
-template <>
-__device__ __forceinline__ cd ldf<float>(const float* p, size_t i) {
-  const float2 v = reinterpret_cast<const float2*>(p)[i];
-  return cd{(double)v.x, (double)v.y};
-}
-template <typename F>
-__device__ __forceinline__ void stf(F* p, size_t i, cd v);
-template <>
-__device__ __forceinline__ void stf<double>(double* p, size_t i, cd v) {
-  st(p, i, v);
-}
-template <>
-__device__ __forceinline__ void stf<float>(float* p, size_t i, cd v) {
-  reinterpret_cast<float2*>(p)[i] = make_float2((float)v.x, (float)v.y);
-}
-
-__device__ __forceinline__ bool active(uint8_t kind, uint8_t depth, int g) {
-  return kind == 1 || (kind == 2 && (int)depth >= g);
-}
-
-// wave64 sum of a complex value
-__device__ __forceinline__ cd wave_sum(cd v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
-  return v;
-}
-// sum over the 16-lane row group (lanes with equal tid>>4)
-__device__ __forceinline__ cd row16_sum(cd v) {
-  for (int o = 8; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 16);
-    v.y += __shfl_xor(v.y, o, 16);
-  }
-  return v;
-}
-// block (256 threads) sum of up to two complex values; result valid in thread 0
-__device__ __forceinline__ void block_sum2(cd& a, cd& b) {
-  __shared__ cd red[2][4];
-  a = wave_sum(a);
-  b = wave_sum(b);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) {
-    red[0][w] = a;
-    red[1][w] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a = cadd(cadd(red[0][0], red[0][1]), cadd(red[0][2], red[0][3]));
-    b = cadd(cadd(red[1][0], red[1][1]), cadd(red[1][2], red[1][3]));
-  }
-}
-
-// SplitMix64 (Steele, Lea & Flood 2014): counter-based 64-bit mixer.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
-__device__ __forceinline__ double u01(uint64_t z) {  // [0,1)
-  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
-}
+using namespace dev;
 
 // ----------------------------------------------------------------- layout
 __global__ void k_to_tile(TileGeom G, int K, const double* __restrict__ nat,
@@ -255,305 +154,6 @@ __global__ __launch_bounds__(256) void k_factor(TileGeom G, int g, const int* __
   }
 }
 
-// ------------------------------------------------------ tile block solve
-// z = M^{-1} r on one tile: forward z_y = r_y - T_y S_{y-1}^{-1} z_{y-1},
-// backward v_y = S_y^{-1} (z_y - T_{y+1} v_{y+1}).  Thread (i, j) holds
-// S_y^{-1}[i][j] for every slice y in registers; rows are reduced over the
-// 16-lane groups.  rl (input) and zl (output, may alias nothing) live in LDS.
-template <typename F>
-struct TileFactor {
-  cd g[16];
-  __device__ __forceinline__ void load(const F* __restrict__ fac, size_t fbase, int sx, int sy) {
-    const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-#pragma unroll
-    for (int y = 0; y < 16; ++y)
-      g[y] = (y < sy && i < sx && j < sx) ? ldf<F>(fac, fbase + (size_t)y * sx * sx + i * sx + j)
-                                          : cmk(0.0, 0.0);
-  }
-};
-
-template <typename F>
-__device__ __forceinline__ void tile_solve(const TileFactor<F>& f, const cd* rl, cd* zl,
-                                           const uint8_t* act, int sx, int sy, double tt) {
-  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-  __shared__ cd row[16];
-  // forward
-  if (threadIdx.x < sx) zl[threadIdx.x] = rl[threadIdx.x];
-  __syncthreads();
-#pragma unroll
-  for (int y = 1; y < 16; ++y) {
-    if (y < sy) {
-      cd prod = (j < sx) ? cmul(f.g[y - 1], zl[j + sx * (y - 1)]) : cmk(0.0, 0.0);
-      prod = row16_sum(prod);
-      if (j == 0 && i < sx) {
-        const int l = i + sx * y;
-        const bool c = act[l] && act[l - sx];
-        zl[l] = c ? csub(rl[l], cscale(prod, tt)) : rl[l];
-      }
-    }
-    __syncthreads();
-  }
-  // backward (in place over zl)
-#pragma unroll
-  for (int y = 15; y >= 0; --y) {
-    if (y < sy) {
-      if (y < sy - 1) {
-        if (threadIdx.x < sx) {
-          const int l = threadIdx.x + sx * y;
-          const bool c = act[l + sx] && act[l];
-          if (c) row[threadIdx.x] = csub(zl[l], cscale(zl[l + sx], tt));
-          else row[threadIdx.x] = zl[l];
-        }
-      } else {
-        if (threadIdx.x < sx) row[threadIdx.x] = zl[threadIdx.x + sx * y];
-      }
-      __syncthreads();
-      cd prod = (j < sx) ? cmul(f.g[y], row[j]) : cmk(0.0, 0.0);
-      prod = row16_sum(prod);
-      if (j == 0 && i < sx) zl[i + sx * y] = prod;
-      __syncthreads();
-    }
-  }
-}
-
-// ---------------------------------------------------------------- COCG
-// Preconditioned conjugate orthogonal conjugate gradient (the complex-
-// symmetric CG: every inner product bilinear) for A_g x = b, A_g the lattice
-// restricted to the sites active in graph g, M the tile blocks of A_g.
-// Items (domain, frequency) iterate in lock step; converged ones are skipped.
-struct CocgArgs {
-  TileGeom G;
-  int g;
-  const int* tile_node;
-  int n_nodes;
-  const int* item_skip;   // Lanczos-level "stopped" flags (may be null)
-  CocgState st;           // per-item scalars
-  const double* d;
-  double *x, *r, *z, *p_old, *p_new, *s;
-  double* partial;        // [K*T*2] complex
-  unsigned long long* wctr;
-};
-
-template <typename F>
-__global__ __launch_bounds__(256) void k_cocg_init(CocgArgs a, const double* __restrict__ b,
-                                                   const F* __restrict__ fac) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  const TileGeom& G = a.G;
-  if (a.item_skip && a.item_skip[item]) return;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * G.S;
-  __shared__ cd rl[256], zl[256];
-  __shared__ uint8_t act[256];
-  const int tid = threadIdx.x;
-  cd rv = cmk(0.0, 0.0);
-  if (tid < G.S) {
-    const size_t p = (size_t)t * G.S + tid;
-    const bool ac = active(G.kind[p], G.depth[p], a.g);
-    act[tid] = ac;
-    rv = ac ? ld(b, base + tid) : cmk(0.0, 0.0);
-    rl[tid] = rv;
-  } else if (tid < 256) {
-    act[tid] = 0;
-  }
-  TileFactor<F> f;
-  f.load(fac, ((size_t)k * G.T + t) * (size_t)G.sy * G.sx * G.sx, G.sx, G.sy);
-  __syncthreads();
-  tile_solve<F>(f, rl, zl, act, G.sx, G.sy, G.t);
-  cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
-  if (tid < G.S) {
-    cd zv = act[tid] ? zl[tid] : cmk(0.0, 0.0);
-    st(a.r, base + tid, rv);
-    st(a.z, base + tid, zv);
-    st(a.x, base + tid, cmk(0.0, 0.0));
-    st(a.p_old, base + tid, cmk(0.0, 0.0));
-    rz = cmul(rv, zv);
-    rr = cmk(cabs2(rv), 0.0);
-  }
-  block_sum2(rz, rr);
-  if (tid == 0) {
-    const size_t q = ((size_t)k * G.T + t) * 2;
-    st(a.partial, q, rz);
-    st(a.partial, q + 1, rr);
-  }
-}
-
-// p_new = z + beta p_old ; s = A_g p_new ; partial mu = p_new^T s
-__global__ __launch_bounds__(256) void k_cocg_stencil(CocgArgs a) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.st.done[item]) return;
-  const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t kb = (size_t)k * NP;
-  const size_t base = kb + (size_t)t * G.S;
-  const cd beta = ld(a.st.beta, item);
-  if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[1], (unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
-  __shared__ cd pl[256];
-  const int tid = threadIdx.x;
-  const int sx = G.sx;
-  bool ac = false;
-  cd pn = cmk(0.0, 0.0);
-  if (tid < G.S) {
-    const size_t p = (size_t)t * G.S + tid;
-    ac = active(G.kind[p], G.depth[p], a.g);
-    if (ac) pn = cadd(ld(a.z, base + tid), cmul(beta, ld(a.p_old, base + tid)));
-    pl[tid] = pn;
-    st(a.p_new, base + tid, pn);
-  }
-  __syncthreads();
-  cd mu = cmk(0.0, 0.0), unused = cmk(0.0, 0.0);
-  if (tid < G.S && ac) {
-    const int lx = tid % sx, ly = tid / sx;
-    cd acc = cmul(ld(a.d, base + tid), pn);
-    cd nb = cmk(0.0, 0.0);
-    // -x
-    if (lx > 0) nb = cadd(nb, pl[tid - 1]);
-    else if (G.nbr[t * 4 + 0] >= 0) {
-      const int nt = G.nbr[t * 4 + 0], nl = tid + sx - 1;
-      const size_t np = (size_t)nt * G.S + nl;
-      if (active(G.kind[np], G.depth[np], a.g))
-        nb = cadd(nb, cadd(ld(a.z, kb + np), cmul(beta, ld(a.p_old, kb + np))));
-    }
-    // +x
-    if (lx < sx - 1) nb = cadd(nb, pl[tid + 1]);
-    else if (G.nbr[t * 4 + 1] >= 0) {
-      const int nt = G.nbr[t * 4 + 1], nl = tid - (sx - 1);
-      const size_t np = (size_t)nt * G.S + nl;
-      if (active(G.kind[np], G.depth[np], a.g))
-        nb = cadd(nb, cadd(ld(a.z, kb + np), cmul(beta, ld(a.p_old, kb + np))));
-    }
-    if (G.sy > 1) {
-      // -y
-      if (ly > 0) nb = cadd(nb, pl[tid - sx]);
-      else if (G.nbr[t * 4 + 2] >= 0) {
-        const int nt = G.nbr[t * 4 + 2], nl = tid + sx * (G.sy - 1);
-        const size_t np = (size_t)nt * G.S + nl;
-        if (active(G.kind[np], G.depth[np], a.g))
-          nb = cadd(nb, cadd(ld(a.z, kb + np), cmul(beta, ld(a.p_old, kb + np))));
-      }
-      // +y
-      if (ly < G.sy - 1) nb = cadd(nb, pl[tid + sx]);
-      else if (G.nbr[t * 4 + 3] >= 0) {
-        const int nt = G.nbr[t * 4 + 3], nl = tid - sx * (G.sy - 1);
-        const size_t np = (size_t)nt * G.S + nl;
-        if (active(G.kind[np], G.depth[np], a.g))
-          nb = cadd(nb, cadd(ld(a.z, kb + np), cmul(beta, ld(a.p_old, kb + np))));
-      }
-    }
-    acc = cadd(acc, cscale(nb, G.t));
-    st(a.s, base + tid, acc);
-    mu = cmul(pn, acc);
-  } else if (tid < G.S) {
-    st(a.s, base + tid, cmk(0.0, 0.0));
-  }
-  block_sum2(mu, unused);
-  if (tid == 0) st(a.partial, ((size_t)k * G.T + t) * 2, mu);
-}
-
-// x += alpha p ; r -= alpha s ; z = M^{-1} r ; partials r^T z, |r|^2
-template <typename F>
-__global__ __launch_bounds__(256) void k_cocg_update(CocgArgs a, const F* __restrict__ fac) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.st.done[item]) return;
-  const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * G.S;
-  const cd alpha = ld(a.st.alpha, item);
-  if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[0], (unsigned long long)(G.S * (7 * 16 + 2)) +
-                              (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
-  __shared__ cd rl[256], zl[256];
-  __shared__ uint8_t act[256];
-  const int tid = threadIdx.x;
-  cd rv = cmk(0.0, 0.0);
-  if (tid < G.S) {
-    const size_t p = (size_t)t * G.S + tid;
-    const bool ac = active(G.kind[p], G.depth[p], a.g);
-    act[tid] = ac;
-    if (ac) {
-      const cd pv = ld(a.p_new, base + tid);
-      cd xv = ld(a.x, base + tid);
-      xv = cfma(alpha, pv, xv);
-      st(a.x, base + tid, xv);
-      rv = csub(ld(a.r, base + tid), cmul(alpha, ld(a.s, base + tid)));
-    }
-    rl[tid] = rv;
-  } else {
-    act[tid] = 0;
-  }
-  TileFactor<F> f;
-  f.load(fac, ((size_t)k * G.T + t) * (size_t)G.sy * G.sx * G.sx, G.sx, G.sy);
-  __syncthreads();
-  tile_solve<F>(f, rl, zl, act, G.sx, G.sy, G.t);
-  cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
-  if (tid < G.S) {
-    cd zv = act[tid] ? zl[tid] : cmk(0.0, 0.0);
-    st(a.r, base + tid, rv);
-    st(a.z, base + tid, zv);
-    rz = cmul(rv, zv);
-    rr = cmk(cabs2(rv), 0.0);
-  }
-  block_sum2(rz, rr);
-  if (tid == 0) {
-    const size_t q = ((size_t)k * G.T + t) * 2;
-    st(a.partial, q, rz);
-    st(a.partial, q + 1, rr);
-  }
-}
-
-// Per-item reduction of the tile partials and the scalar recurrences.
-// op 0: after init   rho = r^T z, bn2 = |b|^2, beta = 0, done = (bn2 == 0)
-// op 1: after stencil alpha = rho / mu
-// op 2: after update  converged if |r|^2 <= tol^2 bn2, else beta = rho'/rho
-__global__ void k_cocg_scalars(CocgArgs a, int K, const int* __restrict__ tlo,
-                               const int* __restrict__ thi, int op, double tol2, int it) {
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= K * a.n_nodes) return;
-  const int k = item / a.n_nodes, node = item % a.n_nodes;
-  if (a.item_skip && a.item_skip[item]) {
-    if (op == 0) a.st.done[item] = 1;
-    return;
-  }
-  if (op != 0 && a.st.done[item]) return;
-  cd s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
-  for (int t = tlo[node]; t < thi[node]; ++t) {
-    const size_t q = ((size_t)k * a.G.T + t) * 2;
-    s0 = cadd(s0, ld(a.partial, q));
-    if (op != 1) s1 = cadd(s1, ld(a.partial, q + 1));
-  }
-  if (op == 0) {
-    st(a.st.rho, item, s0);
-    a.st.bn2[item] = s1.x;
-    st(a.st.beta, item, cmk(0.0, 0.0));
-    a.st.iters[item] = 0;
-    a.st.done[item] = (s1.x == 0.0) ? 1 : 0;
-  } else if (op == 1) {
-    if (cabs2(s0) == 0.0) {  // breakdown of the bilinear form: give up on this item
-      a.st.done[item] = 2;
-      return;
-    }
-    st(a.st.alpha, item, cdiv(ld(a.st.rho, item), s0));
-  } else {
-    a.st.iters[item] = it + 1;
-    if (s1.x <= tol2 * a.st.bn2[item]) {
-      a.st.done[item] = 1;
-      return;
-    }
-    const cd rho = ld(a.st.rho, item);
-    st(a.st.beta, item, cdiv(s0, rho));
-    st(a.st.rho, item, s0);
-  }
-}
-
 __global__ void k_count_open(const int* __restrict__ done, int n, int* __restrict__ out) {
   __shared__ int c;
   if (threadIdx.x == 0) c = 0;
@@ -566,20 +166,25 @@ __global__ void k_count_open(const int* __restrict__ done, int n, int* __restric
 }
 
 // -------------------------------------------------------------- Lanczos
+// Items are (domain, frequency) pairs of one level; stopped[item] != 0 makes
+// every kernel skip the item (1 exhausted, 2 step cap, 3 breakdown, 4 done
+// in an earlier attempt).
+
+#define LZ_ITEM()                                   \
+  const int t = blockIdx.x, k = blockIdx.y;         \
+  const int node = a.tile_node[t];                  \
+  if (node < 0) return;                             \
+  const int item = k * a.n_nodes + node;            \
+  if (a.stopped[item]) return;                      \
+  const size_t NP = (size_t)a.G.T * a.G.S;          \
+  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+
 // Start vector: seeded random complex entries on the level's separator
 // sites (the interface C of eq. (4)) of every correction domain, zero
 // elsewhere; partial q^T q.
-__global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict__ q, int only_flag,
-                                                   uint64_t salt) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
+__global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict__ q, uint64_t salt) {
+  LZ_ITEM();
   const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * G.S;
   const int tid = threadIdx.x;
   cd qq = cmk(0.0, 0.0), un = cmk(0.0, 0.0);
   if (tid < G.S) {
@@ -587,7 +192,7 @@ __global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict_
     cd v = cmk(0.0, 0.0);
     if (G.kind[p] == 2 && G.depth[p] == a.level) {
       // keyed by the frequency itself (not its batch slot), the level, the
-      // site and the restart count, so a result does not depend on the batch
+      // site and the attempt, so a result does not depend on the batch
       const uint64_t key = splitmix64(a.seed ^ (salt * 0xD1B54A32D192ED03ULL) ^ a.fkey[k]) ^
                            (((uint64_t)a.level << 40) + (uint64_t)G.site_of[p]);
       const uint64_t h1 = splitmix64(key), h2 = splitmix64(h1 ^ 0xA5A5A5A5A5A5A5A5ULL);
@@ -606,19 +211,11 @@ __global__ void k_freq_keys(const double* __restrict__ omega, int K, uint64_t* _
   fkey[k] = omega ? (uint64_t)__double_as_longlong(omega[k]) : (uint64_t)k;
 }
 
-// dst = src / sqrt(src^T src) (principal root, precomputed in scal) for the
-// flagged items (only_flag) or all open ones
-__global__ void k_lz_scale(LzArgs a, const double* src, double* dst, int only_flag) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
-  const size_t NP = (size_t)a.G.T * a.G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+// q *= scal[item] (the inverse principal root of q^T q)
+__global__ void k_lz_scale(LzArgs a, double* __restrict__ q) {
+  LZ_ITEM();
   const cd inv = ld(a.scal, item);
-  if (threadIdx.x < a.G.S) st(dst, base + threadIdx.x, cmul(ld(src, base + threadIdx.x), inv));
+  if (threadIdx.x < a.G.S) st(q, base + threadIdx.x, cmul(ld(q, base + threadIdx.x), inv));
 }
 
 // Defect of the block solve (eqs. (10)-(12) with the solve of (10) started
@@ -627,13 +224,8 @@ __global__ void k_lz_scale(LzArgs a, const double* src, double* dst, int only_fl
 __global__ __launch_bounds__(256) void k_lz_defect(LzArgs a, const double* __restrict__ q,
                                                    const double* __restrict__ w,
                                                    double* __restrict__ b) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
+  LZ_ITEM();
   const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)k * NP;
   const int tid = threadIdx.x, sx = G.sx;
   if (tid >= G.S) return;
@@ -665,13 +257,7 @@ __global__ __launch_bounds__(256) void k_lz_defect(LzArgs a, const double* __res
 // alpha partials: q^T u and |u|^2
 __global__ __launch_bounds__(256) void k_lz_alpha(LzArgs a, const double* __restrict__ q,
                                                   const double* __restrict__ u) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  const size_t NP = (size_t)a.G.T * a.G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+  LZ_ITEM();
   const int tid = threadIdx.x;
   cd qu = cmk(0.0, 0.0), uu = cmk(0.0, 0.0);
   if (tid < a.G.S) {
@@ -687,46 +273,33 @@ __global__ __launch_bounds__(256) void k_lz_alpha(LzArgs a, const double* __rest
 }
 
 // Three-term recurrence and the streaming diagonal (after eq. (13)):
-// Gacc += alpha_j q_j*q_j + 2 beta_j q_{j-1}*q_j ; r = u - alpha_j q_j - beta_j q_{j-1}
+// D += alpha_j q_j*q_j + 2 beta_j q_{j-1}*q_j ; r = u - alpha_j q_j - beta_j q_{j-1}
 __global__ __launch_bounds__(256) void k_lz_recur(LzArgs a, const double* __restrict__ q,
                                                   const double* __restrict__ qprev,
                                                   const double* __restrict__ u,
-                                                  double* __restrict__ r, double* __restrict__ gacc) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  const size_t NP = (size_t)a.G.T * a.G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+                                                  double* __restrict__ r, double* __restrict__ D) {
+  LZ_ITEM();
   const int tid = threadIdx.x;
   if (tid >= a.G.S) return;
   const cd al = ld(a.alpha, item), be = ld(a.beta, item);
   const cd qv = ld(q, base + tid);
   const cd qp = qprev ? ld(qprev, base + tid) : cmk(0.0, 0.0);
-  cd gv = ld(gacc, base + tid);
+  cd gv = ld(D, base + tid);
   gv = cadd(gv, cmul(al, cmul(qv, qv)));
   gv = cadd(gv, cscale(cmul(be, cmul(qp, qv)), 2.0));
-  st(gacc, base + tid, gv);
+  st(D, base + tid, gv);
   cd rv = csub(ld(u, base + tid), cmul(al, qv));
   rv = csub(rv, cmul(be, qp));
   st(r, base + tid, rv);
 }
 
-// Classical Gram-Schmidt, bilinear: h_i = Q_i^T r for i <= j.  Each wave
+// Classical Gram-Schmidt, bilinear: h_i = Q_i^T r for i < nvec.  Each wave
 // takes every fourth basis vector of the tile; lanes cover 4 sites each.
 __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restrict__ Q,
                                                  size_t qstride, int nvec,
-                                                 const double* __restrict__ r, int only_flag) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
+                                                 const double* __restrict__ r) {
+  LZ_ITEM();
   const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * G.S;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (a.wctr && threadIdx.x == 0)
     atomicAdd(&a.wctr[3], (unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
@@ -750,13 +323,12 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   }
 }
 
-// h[item][i] = sum over the domain's tiles of the partials
+// h[item][i] = sum over the domain's tiles of the partials (fixed order)
 __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
-                             const int* __restrict__ thi, int nvec, int only_flag) {
+                             const int* __restrict__ thi, int nvec) {
   const int item = blockIdx.y;
   const int k = item / a.n_nodes, node = item % a.n_nodes;
   if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += gridDim.x * blockDim.x) {
     cd s = cmk(0.0, 0.0);
     for (int t = tlo[node]; t < thi[node]; ++t)
@@ -765,21 +337,17 @@ __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
   }
 }
 
-// r -= sum_i h_i Q_i
+// r -= sum_i h_i Q_i, and D += (sum_i h_i Q_i) * q_j: with full
+// re-orthogonalization the matrix of X in the computed basis is the
+// Hessenberg H = T + (re-orthogonalization coefficients); its column j
+// above the tridiagonal band is added here so that diag(Q H Q^T) is formed.
 __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __restrict__ Q,
                                                     size_t qstride, int nvec,
-                                                    double* __restrict__ r, int only_flag) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
+                                                    double* __restrict__ r, double* __restrict__ D) {
+  LZ_ITEM();
   const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * G.S;
   if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[2], (unsigned long long)(nvec + 2) * G.S * 16 + 16ull * nvec);
+    atomicAdd(&a.wctr[2], (unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec);
   __shared__ cd hl[1024];
   const double* hs = a.h + (size_t)item * a.hstride * 2;
   for (int i = threadIdx.x; i < nvec && i < 1024; i += blockDim.x) hl[i] = ld(hs, i);
@@ -792,19 +360,13 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
     acc = cfma(hv, ld(Q + (size_t)i * qstride, base + tid), acc);
   }
   st(r, base + tid, csub(ld(r, base + tid), acc));
+  const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
+  st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
 }
 
 // partials |r|^2 and r^T r
-__global__ __launch_bounds__(256) void k_lz_norms(LzArgs a, const double* __restrict__ r,
-                                                  int only_flag) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item]) return;
-  if (only_flag && !a.restart[item]) return;
-  const size_t NP = (size_t)a.G.T * a.G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+__global__ __launch_bounds__(256) void k_lz_norms(LzArgs a, const double* __restrict__ r) {
+  LZ_ITEM();
   const int tid = threadIdx.x;
   cd rr = cmk(0.0, 0.0), rtr = cmk(0.0, 0.0);
   if (tid < a.G.S) {
@@ -821,32 +383,23 @@ __global__ __launch_bounds__(256) void k_lz_norms(LzArgs a, const double* __rest
 
 // q_{j+1} = r / beta_{j+1}
 __global__ void k_lz_next(LzArgs a, const double* __restrict__ r, double* __restrict__ qn) {
-  const int t = blockIdx.x, k = blockIdx.y;
-  const int node = a.tile_node[t];
-  if (node < 0) return;
-  const int item = k * a.n_nodes + node;
-  if (a.stopped[item] || a.restart[item]) return;
-  const size_t NP = (size_t)a.G.T * a.G.S;
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+  LZ_ITEM();
   if (threadIdx.x >= a.G.S) return;
   const cd inv = cdiv(cmk(1.0, 0.0), ld(a.beta, item));
   st(qn, base + threadIdx.x, cmul(ld(r, base + threadIdx.x), inv));
 }
 
 // Per-item scalar steps of the Lanczos recurrence.
-//   op 0: start      scal = 1/sqrt(q^T q)
-//   op 1: alpha      alpha = q^T u, unorm2 = |u|^2
-//   op 2: norms      stop / restart decision, beta_{j+1} = sqrt(r^T r)
-//   op 3: restart    scal = 1/sqrt(r^T r) of the fresh re-orthogonalized
-//                    vector, beta_{j+1} = 0 (T splits into blocks)
+//   op 0: start   scal = 1/sqrt(q^T q)
+//   op 1: alpha   alpha = q^T u, unorm2 = |u|^2
+//   op 2: norms   stop test, beta_{j+1} = principal sqrt(r^T r)
 __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
                              const int* __restrict__ thi, const int* __restrict__ mcap, int op,
-                             int j, double tol, double brk, int max_restarts) {
+                             int j, double tol, double brk) {
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= K * a.n_nodes) return;
   const int k = item / a.n_nodes, node = item % a.n_nodes;
   if (a.stopped[item]) return;
-  if (op == 3 && !a.restart[item]) return;
   const int per = (op == 0) ? 1 : 2;
   cd s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
   for (int t = tlo[node]; t < thi[node]; ++t) {
@@ -854,27 +407,29 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     s0 = cadd(s0, ld(a.partial, q));
     if (per == 2) s1 = cadd(s1, ld(a.partial, q + 1));
   }
-  if (op == 0 || op == 3) {
-    const cd qq = (op == 0) ? s0 : s1;  // q^T q of the new start vector
-    if (cabs2(qq) == 0.0) {             // empty interface or a degenerate draw
-      a.stopped[item] = (op == 0) ? 1 : 3;
+  if (op == 0) {
+    if (cabs2(s0) == 0.0) {  // degenerate draw
+      a.stopped[item] = 3;
       return;
     }
-    st(a.scal, item, cdiv(cmk(1.0, 0.0), csqrt_p(qq)));
-    if (op == 3) st(a.beta, item, cmk(0.0, 0.0));
+    st(a.scal, item, cdiv(cmk(1.0, 0.0), csqrt_p(s0)));
+    st(a.beta, item, cmk(0.0, 0.0));
+    a.steps[item] = 0;
+    a.umax2[item] = 0.0;
     return;
   }
   if (op == 1) {
     st(a.alpha, item, s0);
     a.unorm2[item] = s1.x;
+    a.umax2[item] = fmax(a.umax2[item], s1.x);
     return;
   }
-  // op 2
   const int steps = j + 1;
   a.steps[item] = steps;
-  a.restart[item] = 0;
+  // exhausted when the new residual is at the noise level of this step's
+  // X-matvec, or (backstop) far below the largest |u| seen, an estimate of |X|
   const double rn = sqrt(s0.x), un = sqrt(a.unorm2[item]);
-  if (rn <= tol * un || un == 0.0) {
+  if (rn <= tol * un || rn <= 1e-3 * tol * sqrt(a.umax2[item]) || un == 0.0) {
     a.stopped[item] = 1;  // the Krylov space of X is exhausted: T_j is complete
     return;
   }
@@ -883,16 +438,38 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     return;
   }
   if (sqrt(cabs2(s1)) <= brk * s0.x) {
-    // serious breakdown of the bilinear form: restart from a fresh vector
-    if (a.nrestart[item] >= max_restarts) {
-      a.stopped[item] = 3;
-      return;
-    }
-    a.nrestart[item] += 1;
-    a.restart[item] = 1;
+    a.stopped[item] = 3;  // serious breakdown of the bilinear form: redo the item
     return;
   }
   st(a.beta, item, csqrt_p(s1));
+}
+
+// Between attempts: clear D on the tiles of items that broke down (stopped
+// == 3) ...
+__global__ void k_lz_clear_bad(LzArgs a, double* __restrict__ D) {
+  const int t = blockIdx.x, k = blockIdx.y;
+  const int node = a.tile_node[t];
+  if (node < 0) return;
+  const int item = k * a.n_nodes + node;
+  if (a.stopped[item] != 3) return;
+  const size_t NP = (size_t)a.G.T * a.G.S;
+  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+  if (threadIdx.x < a.G.S) st(D, base + threadIdx.x, cmk(0.0, 0.0));
+}
+// ... then reopen those items and park the finished ones
+__global__ void k_lz_reopen(LzArgs a, int n_items) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= n_items) return;
+  a.stopped[item] = (a.stopped[item] == 3) ? 0 : 4;
+}
+
+// G += D over the level's domains
+__global__ void k_add_into(LzArgs a, const double* __restrict__ D, double* __restrict__ G) {
+  const int t = blockIdx.x, k = blockIdx.y;
+  if (a.tile_node[t] < 0) return;
+  const size_t NP = (size_t)a.G.T * a.G.S;
+  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+  if (threadIdx.x < a.G.S) st(G, base + threadIdx.x, cadd(ld(G, base + threadIdx.x), ld(D, base + threadIdx.x)));
 }
 
 }  // namespace
@@ -928,46 +505,17 @@ void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const 
   }
 }
 
-void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
-  CocgArgs a{L.G, L.g, L.tile_node, L.n_nodes, L.item_skip, L.st, L.d,
-             L.x, L.r, L.z, L.p_old, L.p_new, L.s, L.partial, L.wctr};
-  dim3 grid = tiles_grid(L.G, L.K);
-  if (L.fp32) k_cocg_init<float><<<grid, 256, 0, s>>>(a, b, (const float*)L.fac);
-  else k_cocg_init<double><<<grid, 256, 0, s>>>(a, b, (const double*)L.fac);
-}
-void launch_cocg_stencil(const CocgLaunch& L, hipStream_t s) {
-  CocgArgs a{L.G, L.g, L.tile_node, L.n_nodes, L.item_skip, L.st, L.d,
-             L.x, L.r, L.z, L.p_old, L.p_new, L.s, L.partial, L.wctr};
-  k_cocg_stencil<<<tiles_grid(L.G, L.K), 256, 0, s>>>(a);
-}
-void launch_cocg_update(const CocgLaunch& L, hipStream_t s) {
-  CocgArgs a{L.G, L.g, L.tile_node, L.n_nodes, L.item_skip, L.st, L.d,
-             L.x, L.r, L.z, L.p_old, L.p_new, L.s, L.partial, L.wctr};
-  dim3 grid = tiles_grid(L.G, L.K);
-  if (L.fp32) k_cocg_update<float><<<grid, 256, 0, s>>>(a, (const float*)L.fac);
-  else k_cocg_update<double><<<grid, 256, 0, s>>>(a, (const double*)L.fac);
-}
-void launch_cocg_scalars(const CocgLaunch& L, const int* tlo, const int* thi, int op, double tol2,
-                         int it, hipStream_t s) {
-  CocgArgs a{L.G, L.g, L.tile_node, L.n_nodes, L.item_skip, L.st, L.d,
-             L.x, L.r, L.z, L.p_old, L.p_new, L.s, L.partial, L.wctr};
-  int n = L.K * L.n_nodes;
-  k_cocg_scalars<<<(n + 127) / 128, 128, 0, s>>>(a, L.K, tlo, thi, op, tol2, it);
-}
 void launch_count_open(const int* done, int n, int* out, hipStream_t s) {
   k_count_open<<<1, 256, 0, s>>>(done, n, out);
 }
-
 void launch_freq_keys(const double* omega, int K, uint64_t* fkey, hipStream_t s) {
   k_freq_keys<<<(K + 63) / 64, 64, 0, s>>>(omega, K, fkey);
 }
-void launch_lz_random(const LzArgs& a, int K, double* q, int only_flag, uint64_t salt,
-                      hipStream_t s) {
-  k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, only_flag, salt);
+void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s) {
+  k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, salt);
 }
-void launch_lz_scale(const LzArgs& a, int K, const double* src, double* dst, int only_flag,
-                     hipStream_t s) {
-  k_lz_scale<<<tiles_grid(a.G, K), 256, 0, s>>>(a, src, dst, only_flag);
+void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s) {
+  k_lz_scale<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q);
 }
 void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,
                       hipStream_t s) {
@@ -977,32 +525,40 @@ void launch_lz_alpha(const LzArgs& a, int K, const double* q, const double* u, h
   k_lz_alpha<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, u);
 }
 void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qprev, const double* u,
-                     double* r, double* gacc, hipStream_t s) {
-  k_lz_recur<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, qprev, u, r, gacc);
+                     double* r, double* D, hipStream_t s) {
+  k_lz_recur<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, qprev, u, r, D);
 }
 void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
-                    const double* r, int only_flag, hipStream_t s) {
-  k_cgs_dot<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, only_flag);
+                    const double* r, hipStream_t s) {
+  k_cgs_dot<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r);
 }
 void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
-                       int only_flag, hipStream_t s) {
+                       hipStream_t s) {
   dim3 grid((nvec + 255) / 256, K * a.n_nodes);
-  k_cgs_reduce<<<grid, 256, 0, s>>>(a, K, tlo, thi, nvec, only_flag);
+  k_cgs_reduce<<<grid, 256, 0, s>>>(a, K, tlo, thi, nvec);
 }
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
-                       int only_flag, hipStream_t s) {
-  k_cgs_update<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, only_flag);
+                       double* D, hipStream_t s) {
+  k_cgs_update<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, D);
 }
-void launch_lz_norms(const LzArgs& a, int K, const double* r, int only_flag, hipStream_t s) {
-  k_lz_norms<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r, only_flag);
+void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s) {
+  k_lz_norms<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r);
 }
 void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s) {
   k_lz_next<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r, qn);
 }
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
-                       int op, int j, double tol, double brk, int max_restarts, hipStream_t s) {
+                       int op, int j, double tol, double brk, hipStream_t s) {
   int n = K * a.n_nodes;
-  k_lz_scalars<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, mcap, op, j, tol, brk, max_restarts);
+  k_lz_scalars<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, mcap, op, j, tol, brk);
+}
+void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s) {
+  k_lz_clear_bad<<<tiles_grid(a.G, K), 256, 0, s>>>(a, D);
+  const int n = K * a.n_nodes;
+  k_lz_reopen<<<(n + 127) / 128, 128, 0, s>>>(a, n);
+}
+void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s) {
+  k_add_into<<<tiles_grid(a.G, K), 256, 0, s>>>(a, D, G);
 }
 
 }  // namespace dyson

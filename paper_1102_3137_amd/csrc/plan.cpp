@@ -18,8 +18,8 @@ dyson_opts default_opts() {
   o.max_rank = 0;
   o.extra_steps = 10;
   o.max_inner_iters = 2000;
-  o.inner_tol = 1e-13;
-  o.lanczos_tol = 1e-10;
+  o.inner_tol = 1e-14;
+  o.lanczos_tol = 1e-11;
   o.seed = 0x5eedULL;
   o.profile = 0;
   return o;

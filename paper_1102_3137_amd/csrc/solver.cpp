@@ -115,9 +115,14 @@ struct dyson_plan {
   double *hpart = nullptr, *h = nullptr;
   int hstride = 1;
   CocgState cst{};
-  int *lz_stopped = nullptr, *lz_restart = nullptr, *lz_nrestart = nullptr, *lz_steps = nullptr;
-  double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_scal = nullptr;
+  int *lz_stopped = nullptr, *lz_steps = nullptr;
+  double* Dl = nullptr;     // diagonal correction of the level being run
+  double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
+         *lz_scal = nullptr;
   int* d_count = nullptr;
+  double* rho2 = nullptr;   // inner solves: r^T z of the last two iterations per item
+  double* partS = nullptr;  // inner solves: per-unit p^T A p
+  std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
   int* h_count = nullptr;  // pinned
   unsigned long long* d_prof = nullptr;
   uint64_t* d_fkey = nullptr;
@@ -126,10 +131,20 @@ struct dyson_plan {
   long long stat_inner = 0;
   int stat_inner_max = 0;
   int stat_restarts = 0;
+  int stat_capped = 0;      // items stopped by the step cap before exhaustion
   dyson_status pending = DYSON_OK;
 };
 
 namespace {
+
+// Lanczos step cap of a domain with interface size m: the paper allows 5-10
+// steps beyond m for m ~ 100; bilinear Lanczos in floating point needs more
+// as m grows (m + 11 observed at m = 128), so the allowance scales as m/8.
+int step_cap(int m, const dyson_opts& o) {
+  int c = m + std::max(o.extra_steps, (m + 7) / 8);
+  if (o.max_rank > 0) c = std::min(c, o.max_rank);
+  return c;
+}
 
 void free_workspace(dyson_plan* p) {
   for (void* a : p->allocs) (void)hipFree(a);
@@ -165,6 +180,7 @@ dyson_status ensure_workspace(dyson_plan* p, int K) {
   CHECKED(walloc(p, &p->s, V));
   CHECKED(walloc(p, &p->rhs, V));
   CHECKED(walloc(p, &p->R, V));
+  CHECKED(walloc(p, &p->Dl, V));
   const int nq = P.levels.empty() ? 1 : (p->kcap + 1);
   CHECKED(walloc(p, &p->Q, V * (size_t)nq));
   const size_t fe = (size_t)K * P.T * P.sy * P.sx * P.sx * 2;  // reals per factor set
@@ -185,17 +201,15 @@ dyson_status ensure_workspace(dyson_plan* p, int K) {
   CHECKED(walloc(p, &p->h, ni * p->hstride * 2));
   CHECKED(walloc(p, &p->cst.done, ni));
   CHECKED(walloc(p, &p->cst.iters, ni));
-  CHECKED(walloc(p, &p->cst.rho, ni * 2));
-  CHECKED(walloc(p, &p->cst.alpha, ni * 2));
-  CHECKED(walloc(p, &p->cst.beta, ni * 2));
   CHECKED(walloc(p, &p->cst.bn2, ni));
+  CHECKED(walloc(p, &p->rho2, ni * 4));
+  CHECKED(walloc(p, &p->partS, (size_t)K * P.T * 2));
   CHECKED(walloc(p, &p->lz_stopped, ni));
-  CHECKED(walloc(p, &p->lz_restart, ni));
-  CHECKED(walloc(p, &p->lz_nrestart, ni));
   CHECKED(walloc(p, &p->lz_steps, ni));
   CHECKED(walloc(p, &p->lz_alpha, ni * 2));
   CHECKED(walloc(p, &p->lz_beta, ni * 2));
   CHECKED(walloc(p, &p->lz_unorm2, ni));
+  CHECKED(walloc(p, &p->lz_umax2, ni));
   CHECKED(walloc(p, &p->lz_scal, ni * 2));
   CHECKED(walloc(p, &p->d_count, 4));
   CHECKED(walloc(p, &p->d_prof, 8));
@@ -258,7 +272,9 @@ struct Run {
     return DYSON_OK;
   }
 
-  // COCG on graph g for every item of `level`, x = A_g^{-1} b.
+  // COCG on graph g for every item of `level`, x = A_g^{-1} b.  Two launches
+  // per iteration; the host polls the device's open-item count only near the
+  // iteration count the previous solve of the same kind needed.
   dyson_status cocg(int level, int g, const void* fac, const double* b, double* x) {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
@@ -277,38 +293,45 @@ struct Run {
     c.p_old = p->p0;
     c.p_new = p->p1;
     c.s = p->s;
-    c.partial = p->partial;
     c.fac = fac;
     c.fp32 = HP.opts.precision == DYSON_PREC_MIXED;
     c.wctr = p->prof.on ? p->d_prof : nullptr;
-    const double tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
-    const int n_items = K * L.n;
+    c.tlo = L.tlo;
+    c.thi = L.thi;
+    c.n_items = K * L.n;
+    c.partS = p->partS;
+    c.partU = p->partial;
+    c.rho2 = p->rho2;
+    c.tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
+    const int slot = 2 * level + (g == level ? 0 : 1);
+    if ((int)p->pred.size() <= slot) p->pred.resize(slot + 1, 0);
     launch_cocg_init(c, b, s);
-    launch_cocg_scalars(c, L.tlo, L.thi, 0, tol2, 0, s);
-    int it = 0, open = n_items;
-    for (it = 0; it < HP.opts.max_inner_iters; ++it) {
-      timed(1, [&] { launch_cocg_stencil(c, s); });
-      launch_cocg_scalars(c, L.tlo, L.thi, 1, tol2, it, s);
-      timed(0, [&] { launch_cocg_update(c, s); });
-      launch_cocg_scalars(c, L.tlo, L.thi, 2, tol2, it, s);
+    launch_cocg_check(c, 0, p->d_count, s);
+    const int maxit = HP.opts.max_inner_iters;
+    int it = 0, open = 1;
+    int check_at = std::max(1, p->pred[slot] - 1);
+    while (it < maxit) {
+      timed(1, [&] { launch_cocg_stencil(c, it, s); });
+      timed(0, [&] { launch_cocg_update(c, it, s); });
       std::swap(c.p_old, c.p_new);
-      const int n = it + 1;
-      if (n <= 2 || (n % 4) == 0) {
-        CHECKED(count_open(p->cst.done, n_items, &open));
+      ++it;
+      if (it >= check_at || it == maxit) {
+        launch_cocg_check(c, it, p->d_count, s);
+        HIPC(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        open = p->h_count[0];
         if (open == 0) break;
+        check_at = it + (it < 8 ? 1 : 2);
       }
     }
     HIPC(hipGetLastError());
-    if (it == HP.opts.max_inner_iters) {
-      CHECKED(count_open(p->cst.done, n_items, &open));
-      if (open) {
-        p->pending = DYSON_ENOCONV;
-        g_err = "inner COCG solve hit max_inner_iters";
-      }
+    if (open != 0) {
+      p->pending = DYSON_ENOCONV;
+      g_err = "inner COCG solve hit max_inner_iters";
     }
-    const int done_it = std::min(it + 1, HP.opts.max_inner_iters);
-    p->stat_inner += done_it;
-    p->stat_inner_max = std::max(p->stat_inner_max, done_it);
+    p->pred[slot] = it;
+    p->stat_inner += it;
+    p->stat_inner_max = std::max(p->stat_inner_max, it);
     return DYSON_OK;
   }
 
@@ -321,12 +344,11 @@ struct Run {
     a.seed = P().opts.seed;
     a.fkey = p->d_fkey;
     a.stopped = p->lz_stopped;
-    a.restart = p->lz_restart;
-    a.nrestart = p->lz_nrestart;
     a.steps = p->lz_steps;
     a.alpha = p->lz_alpha;
     a.beta = p->lz_beta;
     a.unorm2 = p->lz_unorm2;
+    a.umax2 = p->lz_umax2;
     a.scal = p->lz_scal;
     a.partial = p->partial;
     a.hpart = p->hpart;
@@ -339,8 +361,6 @@ struct Run {
   dyson_status reset_items(int level) {
     const size_t ni = (size_t)K * p->lv[level].n;
     HIPC(hipMemsetAsync(p->lz_stopped, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(p->lz_restart, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(p->lz_nrestart, 0, ni * sizeof(int), s));
     HIPC(hipMemsetAsync(p->lz_steps, 0, ni * sizeof(int), s));
     HIPC(hipMemsetAsync(p->lz_beta, 0, ni * 2 * sizeof(double), s));
     return DYSON_OK;
@@ -358,72 +378,80 @@ struct Run {
     return DYSON_OK;
   }
 
-  void cgs2(const LzArgs& a, const DevLevel& L, int nvec, int only_flag) {
+  void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
-      timed(3, [&] { launch_cgs_dot(a, K, p->Q, qstride, nvec, p->R, only_flag, s); });
-      launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, only_flag, s);
-      timed(2, [&] { launch_cgs_update(a, K, p->Q, qstride, nvec, p->R, only_flag, s); });
+      timed(3, [&] { launch_cgs_dot(a, K, p->Q, qstride, nvec, p->R, s); });
+      launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, s);
+      timed(2, [&] { launch_cgs_update(a, K, p->Q, qstride, nvec, p->R, p->Dl, s); });
     }
   }
 
-  // One correction level: bilinear Lanczos on X for every (domain, frequency).
+  // One correction level: bilinear Lanczos on X for every (domain, frequency),
+  // diag(Q H Q^T) gathered in Dl and added to the running diagonal at the end.
+  // An item whose bilinear form breaks down is redone from a fresh start
+  // vector (its partial diagonal is discarded), at most twice.
   dyson_status lanczos_level(int level, std::vector<int>* steps_out) {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
     const size_t V = (size_t)K * HP.T * HP.S * 2;
     auto Qj = [&](int j) { return p->Q + (size_t)j * V; };
     CHECKED(reset_items(level));
+    HIPC(hipMemsetAsync(p->Dl, 0, V * sizeof(double), s));
     LzArgs a = lz_args(level);
     const int n_items = K * L.n;
-    // start vector, normalized in the bilinear "norm"
-    launch_lz_random(a, K, Qj(0), 0, 0, s);
-    launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 0, 0, HP.opts.lanczos_tol, 0.0, 0, s);
-    launch_lz_scale(a, K, Qj(0), Qj(0), 0, s);
-    HIPC(hipGetLastError());
-    const double brk = 1e-8;
-    const int max_restarts = 8;
+    const double brk = 1e-6;  // |r^T r| <= brk |r|^2 would give |q| >= 1e3: redo the item
     int kmax = 0;
-    for (int m : HP.levels[level].m) kmax = std::max(kmax, m);
-    kmax += HP.opts.extra_steps;
-    if (HP.opts.max_rank > 0) kmax = std::min(kmax, HP.opts.max_rank);
+    for (int m : HP.levels[level].m) kmax = std::max(kmax, step_cap(m, HP.opts));
     kmax = std::min(kmax, p->kcap);
-    for (int j = 0; j < kmax; ++j) {
-      int open = 0;
-      CHECKED(count_open(p->lz_stopped, n_items, &open));
-      if (open == 0) break;
-      const double* q = Qj(j);
-      CHECKED(xmatvec(level, q, p->xH));
-      launch_lz_alpha(a, K, q, p->xH, s);
-      launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 1, j, HP.opts.lanczos_tol, brk, max_restarts, s);
-      launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, p->xH, p->R, p->gacc, s);
-      cgs2(a, L, j + 1, 0);
-      launch_lz_norms(a, K, p->R, 0, s);
-      launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, max_restarts, s);
-      if (j + 1 < p->kcap) {
-        launch_lz_next(a, K, p->R, Qj(j + 1), s);
-        // restart path (items flagged by a serious breakdown only)
-        launch_lz_random(a, K, p->R, 1, (uint64_t)(j + 1), s);
-        cgs2(a, L, j + 1, 1);
-        launch_lz_norms(a, K, p->R, 1, s);
-        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 3, j, HP.opts.lanczos_tol, brk, max_restarts, s);
-        launch_lz_scale(a, K, p->R, Qj(j + 1), 1, s);
-      }
+    std::vector<int> st(n_items), stop(n_items);
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      // start vector, normalized in the bilinear "norm"
+      launch_lz_random(a, K, Qj(0), (uint64_t)attempt, s);
+      launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 0, 0, HP.opts.lanczos_tol, brk, s);
+      launch_lz_scale(a, K, Qj(0), s);
       HIPC(hipGetLastError());
-    }
-    // statistics
-    std::vector<int> st(n_items), nr(n_items), stop(n_items);
-    HIPC(hipMemcpyAsync(st.data(), p->lz_steps, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(nr.data(), p->lz_nrestart, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(stop.data(), p->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    for (int i = 0; i < n_items; ++i) {
-      p->stat_restarts += nr[i];
-      if (stop[i] == 3) {
+      for (int j = 0; j < kmax; ++j) {
+        int open = 0;
+        CHECKED(count_open(p->lz_stopped, n_items, &open));
+        if (open == 0) break;
+        const double* q = Qj(j);
+        CHECKED(xmatvec(level, q, p->xH));
+        launch_lz_alpha(a, K, q, p->xH, s);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 1, j, HP.opts.lanczos_tol, brk, s);
+        launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, p->xH, p->R, p->Dl, s);
+        cgs2(a, L, j + 1);
+        launch_lz_norms(a, K, p->R, s);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, s);
+        if (j + 1 < p->kcap) launch_lz_next(a, K, p->R, Qj(j + 1), s);
+        HIPC(hipGetLastError());
+      }
+      HIPC(hipMemcpyAsync(stop.data(), p->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(st.data(), p->lz_steps, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      int bad = 0;
+      for (int i = 0; i < n_items; ++i) {
+        bad += (stop[i] == 3);
+        if (stop[i] == 2) p->stat_capped += 1;
+      }
+      if (std::getenv("DYSON_VERBOSE")) {
+        int hist[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < n_items; ++i) hist[std::min(std::max(stop[i], 0), 4)]++;
+        std::fprintf(stderr, "[dyson] level %d attempt %d: stop codes open=%d exhausted=%d cap=%d breakdown=%d\n",
+                     level, attempt, hist[0], hist[1], hist[2], hist[3]);
+      }
+      if (bad == 0) break;
+      if (attempt == 2) {
         p->pending = DYSON_EBREAKDOWN;
         g_err = "Lanczos breakdown persisted after restarts";
+        break;
       }
+      p->stat_restarts += bad;
+      launch_lz_reopen(a, K, p->Dl, s);
+      HIPC(hipGetLastError());
     }
+    launch_add_into(a, K, p->Dl, p->gacc, s);
+    HIPC(hipGetLastError());
     if (steps_out) *steps_out = st;
     return DYSON_OK;
   }
@@ -471,11 +499,7 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
   p->nmax = 1;
   for (const auto& L : P.levels) {
     p->nmax = std::max(p->nmax, L.n_nodes);
-    for (int m : L.m) {
-      int cap = m + o.extra_steps;
-      if (o.max_rank > 0) cap = std::min(cap, o.max_rank);
-      p->kcap = std::max(p->kcap, cap + 1);
-    }
+    for (int m : L.m) p->kcap = std::max(p->kcap, step_cap(m, o) + 1);
   }
   p->hstride = p->kcap + 1;
   if (ctx) {
@@ -495,11 +519,7 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
       DevLevel d;
       d.n = L.n_nodes;
       std::vector<int> cap(L.n_nodes);
-      for (int i = 0; i < L.n_nodes; ++i) {
-        int c = L.m[i] + o.extra_steps;
-        if (o.max_rank > 0) c = std::min(c, o.max_rank);
-        cap[i] = c;
-      }
+      for (int i = 0; i < L.n_nodes; ++i) cap[i] = step_cap(L.m[i], o);
       CHECKED(dalloc(&d.tile_node, (size_t)P.T));
       CHECKED(dalloc(&d.tlo, (size_t)L.n_nodes));
       CHECKED(dalloc(&d.thi, (size_t)L.n_nodes));
@@ -593,6 +613,7 @@ static dyson_status begin(dyson_plan* p, int K, hipStream_t s) {
   p->stat_inner = 0;
   p->stat_inner_max = 0;
   p->stat_restarts = 0;
+  p->stat_capped = 0;
   p->fac_g[0] = p->fac_g[1] = -1000;  // factors depend on d, which changes per call
   launch_freq_keys(nullptr, K, p->d_fkey, s);
   return DYSON_OK;
@@ -741,7 +762,7 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
     rep->inner_iters = p->stat_inner;
     rep->inner_iters_max = p->stat_inner_max;
     rep->restarts = p->stat_restarts;
-    rep->truncated = (P.opts.max_rank > 0) ? 1 : 0;
+    rep->truncated = p->stat_capped > 0 ? 1 : 0;
     if (p->prof.on) {
       unsigned long long wb[8];
       HIPC(hipMemcpy(wb, p->d_prof, sizeof(wb), hipMemcpyDeviceToHost));

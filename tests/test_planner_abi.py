@@ -35,7 +35,7 @@ def _host_plan(dims, s, part, **kw):
     for a in range(3):
         lat.L[a] = dims[a] if a < len(dims) else 1
     lat.t, lat.mu = -1.0, 0.5
-    o = B.Opts(s, part, kw.get("precision", 0), kw.get("max_rank", 0), 10, 2000, 1e-13, 1e-10,
+    o = B.Opts(s, part, kw.get("precision", 0), kw.get("max_rank", 0), 10, 2000, 1e-14, 1e-11,
                1, 0)
     return B.dyson_plan_create(None, lat, o)
 
