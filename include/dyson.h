@@ -76,7 +76,9 @@ typedef struct {
   double inner_tol;   /* relative residual of the inner solves [1e-14] */
   double lanczos_tol; /* stop when |r|_2 <= lanczos_tol*|u|_2 [1e-11] */
   uint64_t seed;      /* seed of the Lanczos start vectors [0x5eed] */
-  int profile;        /* 1: time the hot kernels with HIP events into the report */
+  int profile;        /* 1: time the dominant kernel (inner-solve update) with HIP
+                         events on the call's stream; 2: every hot kernel class;
+                         algorithmic bytes are counted for all classes [0] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */

@@ -196,7 +196,7 @@ class Plan:
             lat.L[a] = dims[a] if a < len(dims) else 1
         lat.t, lat.mu = float(t), float(mu)
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
-                 inner_tol, lanczos_tol, seed, int(bool(profile)))
+                 inner_tol, lanczos_tol, seed, int(profile))
         self.dims = dims
         self.n_sites = 1
         for x in dims:

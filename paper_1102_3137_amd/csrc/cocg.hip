@@ -77,6 +77,24 @@ struct WaveFactor<float, true> {
   uint32_t gr[16][4], gi[16][4];
   __device__ __forceinline__ void load(const float* fac, size_t fbase, int sx, int sy, int lane) {
     const int i = lane >> 2, c = lane & 3;
+    if (sx == 16) {
+      // full tiles: lane L reads complex64 entries 4L..4L+3 of each slice,
+      // 32 contiguous bytes, the wave 2 KB per slice
+      const float4* f4 = reinterpret_cast<const float4*>(fac + 2 * fbase);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) {
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+        if (y < sy) {
+          a = f4[(size_t)y * 128 + 2 * lane];
+          b = f4[(size_t)y * 128 + 2 * lane + 1];
+        }
+        gr[y][0] = __float_as_uint(a.x); gi[y][0] = __float_as_uint(a.y);
+        gr[y][1] = __float_as_uint(a.z); gi[y][1] = __float_as_uint(a.w);
+        gr[y][2] = __float_as_uint(b.x); gi[y][2] = __float_as_uint(b.y);
+        gr[y][3] = __float_as_uint(b.z); gi[y][3] = __float_as_uint(b.w);
+      }
+      return;
+    }
 #pragma unroll
     for (int y = 0; y < 16; ++y)
 #pragma unroll

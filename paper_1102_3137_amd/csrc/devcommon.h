@@ -119,12 +119,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// sum over the 4 lanes of a quad (lanes 4q..4q+3)
+// DPP quad permutations of a double (lane i of each quad reads lane i^1 or
+// i^2 of the same quad); quad_perm selectors [1,0,3,2] and [2,3,0,1]
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 4 lanes of a quad (lanes 4q..4q+3), every lane gets the sum
 __device__ __forceinline__ cd quad_sum(cd v) {
-  v.x += __shfl_xor(v.x, 1, 64);
-  v.y += __shfl_xor(v.y, 1, 64);
-  v.x += __shfl_xor(v.x, 2, 64);
-  v.y += __shfl_xor(v.y, 2, 64);
+  v.x += dpp_quad<0xB1>(v.x);
+  v.y += dpp_quad<0xB1>(v.y);
+  v.x += dpp_quad<0x4E>(v.x);
+  v.y += dpp_quad<0x4E>(v.y);
   return v;
 }
 

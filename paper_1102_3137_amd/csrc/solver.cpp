@@ -234,7 +234,10 @@ struct Run {
   template <typename Fn>
   void timed(int c, Fn fn) {
     Prof& pr = p->prof;
-    if (!pr.on) {
+    // profile = 1: events around the inner-solve update kernel only (the
+    // dominant kernel); profile >= 2: around every timed kernel class
+    if (!pr.on || (P().opts.profile < 2 && c != 0)) {
+      if (pr.on) pr.launches[c] += 1;
       fn();
       return;
     }
