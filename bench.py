@@ -39,19 +39,24 @@ def kernel_source_hash():
 
 
 def traffic_for(kernel, workload, precision):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/<kernel>_<workload>_<precision>.txt: FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by a plain-copy calibration), if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_hash") != kernel_source_hash():
+        return None
     try:
-        tab = json.load(open(path))
-    except Exception:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
-    ent = tab.get(f"{kernel}|{workload}|{precision}")
-    if not ent or ent.get("source_hash") != kernel_source_hash():
-        return None
-    return ent.get("bytes_per_launch")
 
 
 def cpu_baseline(w, n_freq_sample, max_seconds=30.0):
@@ -87,12 +92,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "mixed16", "fp64"], default="mixed16")
     ap.add_argument("--workload", choices=["square256", "square128", "small32"], default="square256")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the hot kernels with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=8)
+    ap.add_argument("--plain-baseline", action="store_true",
+                    help="also time the plain per-frequency FP64 solve on 4 sampled frequencies")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -114,7 +121,8 @@ def main():
     import torch
 
     import synth
-    from paper_1102_3137_amd import Plan, PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED
+    from paper_1102_3137_amd import (Plan, PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED,
+                                     PREC_MIXED16)
 
     if args.workload == "square256":
         w, s, part = synth.SQUARE_256, 16, PART_NESTED
@@ -122,7 +130,7 @@ def main():
         w, s, part = synth.scaled_square(128, 64), 16, PART_NESTED
     else:
         w, s, part = synth.SMALL_32, 16, PART_SINGLE
-    prec = PREC_MIXED if args.precision == "mixed" else PREC_FP64
+    prec = {"mixed": PREC_MIXED, "mixed16": PREC_MIXED16, "fp64": PREC_FP64}[args.precision]
     dev = torch.device("cuda:0")
     V, om, sig = synth.make_inputs(w)
     tV = torch.from_numpy(V).to(dev)
@@ -184,13 +192,34 @@ def main():
         if not err <= 1e-6:
             value = 0.0   # only results within 1e-6 of the oracle count
 
+    # the plain form: one frequency per call, FP64 factors (sampled, extrapolated)
+    plain = None
+    if args.plain_baseline:
+        pp = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=PREC_FP64)
+        ks = sorted({0, w.n_freq // 3, (2 * w.n_freq) // 3, w.n_freq - 1})
+        secs = []
+        for k in ks:
+            G1 = torch.empty((1, w.n_sites), dtype=torch.complex128, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pp.solve(tV, tom[k:k + 1].contiguous(), tsig[k:k + 1].contiguous(), G1)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            log(f"plain fp64 single frequency k={k}: {secs[-1]:.3f} s")
+        est = sum(secs) / len(secs) * w.n_freq
+        plain = {"value": work / est, "unit": "site*freq/s", "sampled_freqs": ks,
+                 "s_per_freq": [round(x, 3) for x in secs],
+                 "note": "one frequency per call, FP64 factors; mean of the samples x K"}
+        pp.close()
+
     lat_sorted = sorted(lat)
     out = {
         "metric": "G_ii sites*freqs/sec at rel err <= 1e-6 vs FP64 oracle; p50/p99 solve latency",
         "value": value, "unit": "site*freq/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 preconditioner + f64" if prec == PREC_MIXED else "f64",
+        "dtype": {PREC_MIXED: "c64 preconditioner + f64", PREC_MIXED16: "c32 preconditioner + f64",
+                  PREC_FP64: "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": w.name + (", 16x16 subdomains, recursive bisection, full rank"
                                          if part == PART_NESTED else ", 4 subdomains, full rank"),
@@ -199,6 +228,7 @@ def main():
         "latency_s": {"p50": lat_sorted[len(lat) // 2],
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "max_rel_err_sampled": err,
+        "plain_fp64_per_frequency": plain,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

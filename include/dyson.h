@@ -23,7 +23,7 @@
  *   - Errors are status codes; nothing throws across the ABI.  On error the
  *     output buffers are left untouched or partially written and must not
  *     be used; dyson_last_error() gives a message (thread-local).
- *   - Validation returns DYSON_EINVAL: dim not in {1,2}, any L < 1, K < 1,
+ *   - Validation returns DYSON_EINVAL: dim not in {1,2,3}, any L < 1, K < 1,
  *     w_k <= 0, non-finite input, or Im(i w_k - Sigma_i) <= 0 (the last
  *     keeps Im H positive definite, so H and every principal submatrix are
  *     non-singular and the pivot-free factorizations below exist).
@@ -48,27 +48,31 @@ typedef enum {
   DYSON_EUNSUPPORTED = 6 /* valid request this build does not implement */
 } dyson_status;
 
-/* Lattice geometry and hopping (eq. (1)).  Open boundaries only. */
+/* Lattice geometry and hopping (eq. (1)): chain, square (Z=4) or simple
+ * cubic (Z=6) lattice.  Open boundaries only. */
 typedef struct {
-  int dim;       /* 1 or 2 */
+  int dim;       /* 1, 2 or 3 */
   int L[3];      /* extents, unused axes = 1; x fastest */
   double t;      /* hopping: H_ij = t on each nearest-neighbour bond */
   double mu;     /* chemical potential in H_ii */
 } dyson_lattice;
 
 enum { DYSON_PART_NESTED = 0, DYSON_PART_SINGLE = 1 };
-enum { DYSON_PREC_FP64 = 0, DYSON_PREC_MIXED = 1 };
+enum { DYSON_PREC_FP64 = 0, DYSON_PREC_MIXED = 1, DYSON_PREC_MIXED16 = 2 };
 
 /* Method options.  Zero-initialise and set what you need; zero fields take
  * the defaults given in brackets. */
 typedef struct {
-  int leaf_edge;      /* subdomain edge s: separators at p with (p+1)%s==0 [16]; 2..16 */
+  int leaf_edge;      /* subdomain edge s: separators at p with (p+1)%s==0 [16];
+                         2..16 (chain, square), 2..6 (cubic: tiles of s^3 <= 216 sites) */
   int partition;      /* DYSON_PART_NESTED: recursive bisection, alternating axes
                          (end of Sec. II.C); DYSON_PART_SINGLE: one level with
                          every separator at once (Fig. 1) [NESTED] */
-  int precision;      /* DYSON_PREC_FP64, or DYSON_PREC_MIXED: complex64
-                         subdomain factors in the inner preconditioner, FP64
-                         residuals and FP64 Lanczos [FP64] */
+  int precision;      /* DYSON_PREC_FP64; DYSON_PREC_MIXED: complex64 subdomain
+                         factors in the inner preconditioner; DYSON_PREC_MIXED16:
+                         complex32 (FP16 pairs) factors there.  Residuals, the
+                         preconditioner arithmetic, Lanczos, re-orthogonalization
+                         and the diagonal stay FP64 in every mode [FP64] */
   int max_rank;       /* cap on Lanczos steps per domain (truncated rank); 0 = full [0] */
   int extra_steps;    /* steps allowed beyond the interface size m (Sec. II.C):
                          the cap is m + max(extra_steps, ceil(m/8)) [10] */

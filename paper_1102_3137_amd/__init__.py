@@ -6,7 +6,7 @@ include/dyson.h); `binding` marshals arguments to it.  There is no CPU
 fallback: loading fails loudly when the library is missing.
 """
 from .binding import (DysonError, Lattice, Opts, Report, PlanInfo, Plan, load_library,
-                      PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED)
+                      PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED, PREC_MIXED16)
 
 __all__ = ["DysonError", "Lattice", "Opts", "Report", "PlanInfo", "Plan", "load_library",
-           "PART_NESTED", "PART_SINGLE", "PREC_FP64", "PREC_MIXED"]
+           "PART_NESTED", "PART_SINGLE", "PREC_FP64", "PREC_MIXED", "PREC_MIXED16"]

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdyson_mi355x.so")
 
 PART_NESTED, PART_SINGLE = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED16 = 0, 1, 2
 STATUS = {0: "DYSON_OK", 1: "DYSON_EINVAL", 2: "DYSON_ENOMEM", 3: "DYSON_EBREAKDOWN",
           4: "DYSON_ENOCONV", 5: "DYSON_EDEVICE", 6: "DYSON_EUNSUPPORTED"}
 

@@ -114,6 +114,42 @@ struct WaveFactor<float, true> {
   }
 };
 
+// complex32 factors (two FP16 halves per entry) held in registers: 64 VGPRs
+template <>
+struct WaveFactor<__half, true> {
+  uint32_t g[16][4];
+  __device__ __forceinline__ void load(const __half* fac, size_t fbase, int sx, int sy, int lane) {
+    const int i = lane >> 2, c = lane & 3;
+    if (sx == 16) {
+      const uint4* f4 = reinterpret_cast<const uint4*>(fac + 2 * fbase);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) {
+        uint4 a = make_uint4(0u, 0u, 0u, 0u);
+        if (y < sy) a = f4[(size_t)y * 64 + lane];
+        g[y][0] = a.x;
+        g[y][1] = a.y;
+        g[y][2] = a.z;
+        g[y][3] = a.w;
+      }
+      return;
+    }
+    const uint32_t* f1 = reinterpret_cast<const uint32_t*>(fac + 2 * fbase);
+#pragma unroll
+    for (int y = 0; y < 16; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * c + e;
+        g[y][e] = (y < sy && i < sx && j < sx) ? f1[(size_t)y * sx * sx + i * sx + j] : 0u;
+      }
+  }
+  __device__ __forceinline__ cd get(int y, int e, const __half*, size_t, int, int) const {
+    uint32_t a = g[y][e];
+    asm volatile("" : "+v"(a));
+    const __half2 h = *reinterpret_cast<const __half2*>(&a);
+    return cmk((double)__low2float(h), (double)__high2float(h));
+  }
+};
+
 // factors streamed from memory slice by slice (read in both sweeps)
 template <typename F>
 struct WaveFactor<F, false> {
@@ -174,6 +210,49 @@ __device__ __forceinline__ void wave_tile_solve(const WaveFactor<F, REG>& f, con
   }
 }
 
+// Slices wider than 16 sites (planes of cubic tiles): lane i < n owns row i
+// of every S_y^{-1}, read from memory in both sweeps.
+template <typename F>
+__device__ __forceinline__ void wave_tile_solve_rows(const F* fac, size_t fbase, cd* zl,
+                                                     const uint8_t* act, int n, int ns, double tt,
+                                                     int lane) {
+  const size_t nn = (size_t)n * n;
+  wave_sync();
+  for (int y = 1; y < ns; ++y) {
+    if (lane < n) {
+      const size_t row = fbase + (size_t)(y - 1) * nn + (size_t)lane * n;
+      cd acc = cmk(0.0, 0.0);
+      for (int j = 0; j < n; ++j) acc = cfma(ldf<F>(fac, row + j), zl[j + n * (y - 1)], acc);
+      const int l = lane + n * y;
+      if (act[l] && act[l - n]) zl[l] = csub(zl[l], cscale(acc, tt));
+    }
+    wave_sync();
+  }
+  for (int y = ns - 1; y >= 0; --y) {
+    cd acc = cmk(0.0, 0.0);
+    if (lane < n) {
+      const size_t row = fbase + (size_t)y * nn + (size_t)lane * n;
+      for (int j = 0; j < n; ++j) {
+        const int l = j + n * y;
+        cd r = zl[l];
+        if (y < ns - 1 && act[l] && act[l + n]) r = csub(r, cscale(zl[l + n], tt));
+        acc = cfma(ldf<F>(fac, row + j), r, acc);
+      }
+    }
+    wave_sync();
+    if (lane < n) zl[lane + n * y] = acc;
+    wave_sync();
+  }
+}
+
+template <typename F, bool REG>
+__device__ __forceinline__ void tile_solve_any(const WaveFactor<F, REG>& f, const F* fac,
+                                               size_t fbase, cd* zl, const uint8_t* act,
+                                               const TileGeom& G, int lane) {
+  if (G.sx > 16) wave_tile_solve_rows<F>(fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
+  else wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
+}
+
 // ------------------------------------------------------------- kernels
 // r = b (masked to graph g), x = 0, p = 0, z = M^{-1} r;
 // item totals: rho = r^T z, bn2 = |b|^2
@@ -206,7 +285,7 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
   const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
   WaveFactor<F, REG> f;
   f.load(fac, fbase, G.sx, G.sy, u.lane);
-  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, u.lane);
+  tile_solve_any<F, REG>(f, fac, fbase, zl, act, G, u.lane);
   cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -254,11 +333,14 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
     beta = cdiv(rho, ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item));
     if (lead && u.lane == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
   }
-  if (a.wctr && u.lane == 0)
-    atomicAdd(&a.wctr[1], (unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
+  // profiling: the item's lead wave books the algorithmic bytes of all the
+  // item's units (one writer per item and launch: no atomics)
+  if (a.wctr && lead && u.lane == 0)
+    a.wctr[(size_t)1 * a.n_items + u.item] +=
+        (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+        ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
   __shared__ cd psh[WAVES][256];
   cd* pl = psh[u.wave];
-  const int sx = G.sx;
   bool ac[4];
   cd pn[4];
 #pragma unroll
@@ -276,12 +358,6 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   }
   wave_sync();
   cd mu = cmk(0.0, 0.0);
-  // value of p_new at a site of a neighbouring tile (same domain when active)
-  auto halo = [&](int nt, int nl) -> cd {
-    const size_t np = (size_t)nt * G.S + nl;
-    if (!active(G.kind[np], G.depth[np], a.g)) return cmk(0.0, 0.0);
-    return cfma(beta, ld(a.p_old, kb + np), ld(a.z, kb + np));
-  };
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int l = u.lane + 64 * e;
@@ -290,17 +366,18 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
       st(a.s, base + l, cmk(0.0, 0.0));
       continue;
     }
-    const int lx = l % sx, ly = l / sx;
     cd nb = cmk(0.0, 0.0);
-    if (lx > 0) nb = cadd(nb, pl[l - 1]);
-    else if (G.nbr[u.t * 4 + 0] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 0], l + sx - 1));
-    if (lx < sx - 1) nb = cadd(nb, pl[l + 1]);
-    else if (G.nbr[u.t * 4 + 1] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 1], l - (sx - 1)));
-    if (G.sy > 1) {
-      if (ly > 0) nb = cadd(nb, pl[l - sx]);
-      else if (G.nbr[u.t * 4 + 2] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 2], l + sx * (G.sy - 1)));
-      if (ly < G.sy - 1) nb = cadd(nb, pl[l + sx]);
-      else if (G.nbr[u.t * 4 + 3] >= 0) nb = cadd(nb, halo(G.nbr[u.t * 4 + 3], l - sx * (G.sy - 1)));
+    for (int dir = 0; dir < 2 * G.dim; ++dir) {
+      int nt, nl;
+      if (!site_nbr(G, u.t, l, dir, nt, nl)) continue;
+      if (nt == u.t) {
+        nb = cadd(nb, pl[nl]);  // inactive sites hold 0 in pl
+      } else {
+        // p_new at a site of a neighbouring tile (the same domain when active)
+        const size_t np = (size_t)nt * G.S + nl;
+        if (active(G.kind[np], G.depth[np], a.g))
+          nb = cadd(nb, cfma(beta, ld(a.p_old, kb + np), ld(a.z, kb + np)));
+      }
     }
     const cd sv = cfma(ld(a.d, base + l), pn[e], cscale(nb, G.t));
     st(a.s, base + l, sv);
@@ -313,7 +390,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
 // x += alpha p ; r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z,
 // |r|^2 ; converged when |r|^2 <= tol^2 |b|^2, else beta = rho'/rho
 template <typename F, bool REG>
-__global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
+__device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   const Unit u = decode(a);
   if (!u.ok || a.st.done[u.item]) return;
   const TileGeom& G = a.G;
@@ -325,9 +402,10 @@ __global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
     return;
   }
   const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
-  if (a.wctr && u.lane == 0)
-    atomicAdd(&a.wctr[0], (unsigned long long)(G.S * (7 * 16 + 2)) +
-                              (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  if (a.wctr && u.t == a.tlo[u.node] && u.lane == 0)
+    a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+                      ((unsigned long long)(G.S * (7 * 16 + 2)) +
+                       (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
   __shared__ cd zsh[WAVES][256];
   __shared__ cd rsh[WAVES][256];
   __shared__ uint8_t ash[WAVES][256];
@@ -359,7 +437,7 @@ __global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
     zl[l] = rv;
     rl[l] = rv;
   }
-  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, u.lane);
+  tile_solve_any<F, REG>(f, fac, fbase, zl, act, G, u.lane);
   cd rz = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -377,6 +455,17 @@ __global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
     st(a.partU, q, rz);
     st(a.partU, q + 1, rr);
   }
+}
+
+template <typename F, bool REG>
+__global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
+  cocg_update_body<F, REG>(a, it);
+}
+// complex64 register factors: 168 VGPRs, capped for 3 waves per SIMD (the
+// latency of the 2 x 16 slice sweep is what this kernel must hide)
+template <typename F, bool REG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_cocg_update_occ3(CocgLaunch a, int it) {
+  cocg_update_body<F, REG>(a, it);
 }
 
 // One workgroup: convergence bookkeeping after launch `it` (it = 0 follows
@@ -415,6 +504,28 @@ __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* _
   if (threadIdx.x == 0) *open = cnt;
 }
 
+// profiling: fold per-item byte counts [classes][n] into tot[class], zeroing them
+__global__ __launch_bounds__(256) void k_prof_collect(unsigned long long* __restrict__ per_item,
+                                                      int n, int classes, int first_class,
+                                                      unsigned long long* __restrict__ tot) {
+  __shared__ unsigned long long red[256];
+  for (int c = 0; c < classes; ++c) {
+    unsigned long long mine = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      mine += per_item[(size_t)c * n + i];
+      per_item[(size_t)c * n + i] = 0;
+    }
+    red[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[first_class + c] += red[0];
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 static inline unsigned cocg_blocks(const CocgLaunch& L) {
@@ -422,17 +533,30 @@ static inline unsigned cocg_blocks(const CocgLaunch& L) {
 }
 
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
-  if (L.fp32) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  const bool regs = L.G.sx <= 16;  // register-resident factors fit 16-site slices
+  if (L.fp16 && regs) k_cocg_init<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  else if (L.fp16) k_cocg_init<__half, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  else if (L.fp32 && regs) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  else if (L.fp32) k_cocg_init<float, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
   else k_cocg_init<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
 }
 void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s) {
   k_cocg_stencil<<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
 }
+void launch_prof_collect(unsigned long long* per_item, int n, int classes, int first_class,
+                         unsigned long long* tot, hipStream_t s) {
+  k_prof_collect<<<1, 256, 0, s>>>(per_item, n, classes, first_class, tot);
+}
 void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
   k_cocg_check<<<1, 256, 0, s>>>(L, it, open);
 }
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
-  if (L.fp32) k_cocg_update<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  const bool regs = L.G.sx <= 16;
+  if (L.fp16 && regs) k_cocg_update<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  else if (L.fp16) k_cocg_update<__half, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  else if (L.fp32 && regs)
+    k_cocg_update_occ3<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  else if (L.fp32) k_cocg_update<float, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
   else k_cocg_update<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
 }
 

@@ -2,8 +2,11 @@
 // interleaved pairs, loads/stores, wave and block reductions, the
 // activity rule of a graph level and a counter-based random generator.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "kernels.h"
 
 namespace dyson {
 namespace dev {
@@ -51,8 +54,17 @@ __device__ __forceinline__ cd ldf<float>(const float* p, size_t i) {
   const float2 v = reinterpret_cast<const float2*>(p)[i];
   return cd{(double)v.x, (double)v.y};
 }
+template <>
+__device__ __forceinline__ cd ldf<__half>(const __half* p, size_t i) {
+  const __half2 v = reinterpret_cast<const __half2*>(p)[i];
+  return cd{(double)__low2float(v), (double)__high2float(v)};
+}
 template <typename F>
 __device__ __forceinline__ void stf(F* p, size_t i, cd v);
+template <>
+__device__ __forceinline__ void stf<__half>(__half* p, size_t i, cd v) {
+  reinterpret_cast<__half2*>(p)[i] = __floats2half2_rn((float)v.x, (float)v.y);
+}
 template <>
 __device__ __forceinline__ void stf<double>(double* p, size_t i, cd v) {
   st(p, i, v);
@@ -111,6 +123,35 @@ __device__ __forceinline__ double u01(uint64_t z) {  // [0,1)
   return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
+
+// Neighbour of tile-local site l in direction dir (0..5 = -x,+x,-y,+y,-z,+z):
+// the same tile or the adjacent one; false at the lattice edge.
+__device__ __forceinline__ bool site_nbr(const TileGeom& G, int t, int l, int dir, int& nt,
+                                         int& nl) {
+  const int s = G.edge, a = dir >> 1, up = dir & 1;
+  if (a >= G.dim) return false;
+  const int stride = (a == 0) ? 1 : (a == 1 ? s : s * s);
+  const int c = (l / stride) % s;
+  if (up ? (c < s - 1) : (c > 0)) {
+    nt = t;
+    nl = up ? l + stride : l - stride;
+    return true;
+  }
+  nt = G.nbr[t * 6 + dir];
+  if (nt < 0) return false;
+  nl = up ? l - (s - 1) * stride : l + (s - 1) * stride;
+  return true;
+}
+
+// Bond between slice-local sites i and j (a row of a square tile, or a
+// plane of a cubic one).
+__device__ __forceinline__ bool slice_adj(const TileGeom& G, int i, int j) {
+  if (G.dim < 3) return i - j == 1 || j - i == 1;
+  const int s = G.edge;
+  const int xi = i % s, yi = i / s, xj = j % s, yj = j / s;
+  return (yi == yj && (xi - xj == 1 || xj - xi == 1)) ||
+         (xi == xj && (yi - yj == 1 || yj - yi == 1));
+}
 
 // wave-scope fence + barrier: orders LDS traffic between the lanes of one wave
 __device__ __forceinline__ void wave_sync() {

@@ -8,13 +8,15 @@ namespace dyson {
 
 // Read-only geometry of a plan on the device (tile-major layout).
 struct TileGeom {
-  int T, S, sx, sy, N;
+  int T, S, sx, sy, N;   // sy block rows (slices) of sx sites per tile
   double t;
-  const int* nbr;        // [T*4]
+  const int* nbr;        // [T*6]: -x, +x, -y, +y, -z, +z
   const uint8_t* kind;   // [T*S] 0 pad, 1 leaf, 2 separator
   const uint8_t* depth;  // [T*S]
   const int* site_of;    // [T*S] natural index or -1
   const int* pos_of;     // [N]
+  int edge;              // tile edge s (tile = s^dim sites)
+  int dim;               // lattice dimension 1..3
 };
 
 // Per-item scalars of the inner COCG solves (item = k * n_nodes + node).
@@ -36,7 +38,9 @@ struct CocgLaunch {
   double *x, *r, *z, *p_old, *p_new, *s;
   const void* fac;       // tile factors for graph g
   bool fp32;             // factors stored as complex64
-  unsigned long long* wctr;  // profiling: algorithmic bytes per kernel class, or null
+  bool fp16;             // factors stored as complex32 (two FP16 halves)
+  unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (update,
+                             // stencil) booked by each item's lead wave, or null
   const int* tlo;        // [n_nodes] tile range of each domain
   const int* thi;
   int n_items;           // K * n_nodes
@@ -64,7 +68,11 @@ struct LzArgs {
   double* hpart;    // [K*T*hstride] complex
   double* h;        // [K*n_nodes*hstride] complex
   int hstride;
-  unsigned long long* wctr;  // profiling: algorithmic bytes per kernel class, or null
+  const int* tlo;   // [n_nodes] tile range of each domain
+  const int* thi;
+  int n_items;
+  unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (CGS update,
+                             // CGS products) booked by each item's lead block, or null
 };
 
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
@@ -72,12 +80,18 @@ void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, d
 void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat, hipStream_t s);
 void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const double* omega,
                      const double* sigma, double* d, hipStream_t s);
+// Tile block factors of graph g (complex128 / complex64 / complex32 storage).
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
-                   void* fac, bool fp32, double* gdiag, hipStream_t s);
+                   void* fac, bool fp32, bool fp16, hipStream_t s);
+// Leaf factors in complex128 (fac64) and the exact diagonal of every leaf block.
+void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64, double* gdiag,
+                        hipStream_t s);
 
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s);
 void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s);
 void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s);
+void launch_prof_collect(unsigned long long* per_item, int n, int classes, int first_class,
+                         unsigned long long* tot, hipStream_t s);
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s);
 void launch_count_open(const int* done, int n, int* out, hipStream_t s);
 

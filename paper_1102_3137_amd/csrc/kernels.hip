@@ -52,105 +52,144 @@ __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restric
 
 // ------------------------------------------------------ tile factorization
 // Block LDL^T of the tile block restricted to the sites active in graph g,
-// slices = rows of sx sites: S_0 = A_0, S_y = A_y - T_y S_{y-1}^{-1} T_y with
-// T_y = t diag(c_y) the bonds between rows y-1 and y.  The dense inverses
-// S_y^{-1} (sx x sx, complex symmetric, pivot-free because Im > 0) are
-// stored per slice.  With DIAG, the exact diagonal of the tile block's
-// inverse follows from the backward recursion
-// G_yy = S_y^{-1} + S_y^{-1} T_{y+1} G_{y+1,y+1} T_{y+1} S_y^{-1}.
-template <typename F, bool DIAG>
+// block rows = slices of n sites (a row of a square tile, a plane of a cubic
+// one): S_0 = A_0, S_y = A_y - T_y S_{y-1}^{-1} T_y with T_y = t diag(c_y)
+// the bonds between slices y-1 and y.  The dense inverses S_y^{-1} (n x n,
+// complex symmetric, pivot-free because Im > 0) are stored per slice,
+// symmetrized so that lower-precision copies stay exactly symmetric.
+constexpr int NMAX = 36;  // widest slice: a 6 x 6 plane
+
+struct FactorSmem {
+  cd dl[256];
+  uint8_t act[256];
+  cd A[NMAX][NMAX + 1];
+  cd Gp[NMAX][NMAX + 1];
+  cd tmp[NMAX][NMAX + 1];
+};
+
+__device__ __forceinline__ void factor_load(FactorSmem& sm, const TileGeom& G, int g, int t, int k,
+                                            const double* __restrict__ d) {
+  const size_t NP = (size_t)G.T * G.S;
+  for (int l = threadIdx.x; l < G.S; l += blockDim.x) {
+    const size_t p = (size_t)t * G.S + l;
+    sm.dl[l] = ld(d, (size_t)k * NP + p);
+    sm.act[l] = active(G.kind[p], G.depth[p], g) ? 1 : 0;
+  }
+  __syncthreads();
+}
+
+// Forms S_y (into A) and inverts it in place (Gauss-Jordan, no pivoting).
+__device__ __forceinline__ void factor_slice(FactorSmem& sm, const TileGeom& G, int y) {
+  const int n = G.sx, nn = n * n;
+  const double tt = G.t;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    const int li = i + n * y, lj = j + n * y;
+    const bool ai = sm.act[li], aj = sm.act[lj];
+    cd v = cmk(0.0, 0.0);
+    if (i == j) v = ai ? sm.dl[li] : cmk(1.0, 0.0);  // identity rows for inactive sites
+    else if (ai && aj && slice_adj(G, i, j)) v = cmk(tt, 0.0);
+    if (y > 0 && ai && aj && sm.act[li - n] && sm.act[lj - n])
+      v = csub(v, cscale(sm.Gp[i][j], tt * tt));
+    sm.A[i][j] = v;
+  }
+  __syncthreads();
+  for (int q = 0; q < n; ++q) {
+    cd nv[6];
+    int c = 0;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) {
+      const int i = e / n, j = e % n;
+      const cd pinv = cdiv(cmk(1.0, 0.0), sm.A[q][q]);
+      if (i == q && j == q) nv[c] = pinv;
+      else if (i == q) nv[c] = cmul(sm.A[q][j], pinv);
+      else if (j == q) nv[c] = cscale(cmul(sm.A[i][q], pinv), -1.0);
+      else nv[c] = csub(sm.A[i][j], cmul(cmul(sm.A[i][q], sm.A[q][j]), pinv));
+    }
+    __syncthreads();
+    c = 0;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) sm.A[e / n][e % n] = nv[c];
+    __syncthreads();
+  }
+}
+
+template <typename F>
 __global__ __launch_bounds__(256) void k_factor(TileGeom G, int g, const int* __restrict__ tile_node,
-                                                const double* __restrict__ d, F* __restrict__ fac,
-                                                double* __restrict__ gdiag) {
+                                                const double* __restrict__ d, F* __restrict__ fac) {
   const int t = blockIdx.x, k = blockIdx.y;
   if (tile_node && tile_node[t] < 0) return;
-  const int sx = G.sx, sy = G.sy, S = G.S;
-  const size_t NP = (size_t)G.T * G.S;
-  const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
-  __shared__ cd dl[256];
-  __shared__ uint8_t act[256];
-  __shared__ cd A[16][17];
-  __shared__ cd Gp[16][17];
-  __shared__ cd Gall[DIAG ? 16 : 1][16][17];
-  __shared__ cd tmp[16][17];
+  __shared__ FactorSmem sm;
+  factor_load(sm, G, g, t, k, d);
+  const int n = G.sx, nn = n * n;
+  const size_t fbase = ((size_t)k * G.T + t) * (size_t)G.sy * nn;
+  for (int y = 0; y < G.sy; ++y) {
+    factor_slice(sm, G, y);
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      stf<F>(fac, fbase + (size_t)y * nn + e, cscale(cadd(sm.A[i][j], sm.A[j][i]), 0.5));
+      sm.Gp[i][j] = sm.A[i][j];
+    }
+    __syncthreads();
+  }
+}
+
+// Leaf graph (every separator inactive): factors in complex128 and the exact
+// diagonal of each leaf block's inverse (eq. (13), first term) by the backward
+// recursion G_yy = S_y^{-1} + S_y^{-1} T_{y+1} G_{y+1,y+1} T_{y+1} S_y^{-1}.
+__global__ __launch_bounds__(256) void k_factor_diag(TileGeom G, const double* __restrict__ d,
+                                                     double* __restrict__ fac,
+                                                     double* __restrict__ gdiag) {
+  const int t = blockIdx.x, k = blockIdx.y;
+  __shared__ FactorSmem sm;
+  factor_load(sm, G, 255, t, k, d);
+  const int n = G.sx, nn = n * n, ns = G.sy;
   const double tt = G.t;
-  if (tid < S) {
-    size_t p = (size_t)t * S + tid;
-    dl[tid] = ld(d, (size_t)k * NP + p);
-    act[tid] = active(G.kind[p], G.depth[p], g) ? 1 : 0;
-  }
-  __syncthreads();
-  const size_t fbase = ((size_t)k * G.T + t) * (size_t)sy * sx * sx;
-  for (int y = 0; y < sy; ++y) {
-    // assemble the slice block (identity rows for inactive or padded sites)
-    if (i < 16 && j < 16) {
-      cd v = cmk(i == j ? 1.0 : 0.0, 0.0);
-      if (i < sx && j < sx) {
-        const int li = i + sx * y, lj = j + sx * y;
-        const bool ai = act[li], aj = act[lj];
-        v = cmk(0.0, 0.0);
-        if (i == j) v = ai ? dl[li] : cmk(1.0, 0.0);
-        else if ((i - j == 1 || j - i == 1) && ai && aj) v = cmk(tt, 0.0);
-        if (y > 0 && ai && aj && act[i + sx * (y - 1)] && act[j + sx * (y - 1)])
-          v = csub(v, cscale(Gp[i][j], tt * tt));
-      }
-      A[i][j] = v;
-    }
-    __syncthreads();
-    // in-place Gauss-Jordan inversion, no pivoting
-    for (int q = 0; q < sx; ++q) {
-      cd piv = A[q][q], aiq = A[i][q], aqj = A[q][j], aij = A[i][j];
-      __syncthreads();
-      cd pinv = cdiv(cmk(1.0, 0.0), piv);
-      cd nv;
-      if (i == q && j == q) nv = pinv;
-      else if (i == q) nv = cmul(aqj, pinv);
-      else if (j == q) nv = cscale(cmul(aiq, pinv), -1.0);
-      else nv = csub(aij, cmul(cmul(aiq, aqj), pinv));
-      if (i < sx && j < sx) A[i][j] = nv;
-      __syncthreads();
-    }
-    if (i < sx && j < sx) {
-      if (fac) stf<F>(fac, fbase + (size_t)y * sx * sx + i * sx + j, A[i][j]);
-      Gp[i][j] = A[i][j];
-      if (DIAG) Gall[y][i][j] = A[i][j];
+  const size_t NP = (size_t)G.T * G.S;
+  const size_t fbase = ((size_t)k * G.T + t) * (size_t)ns * nn;
+  for (int y = 0; y < ns; ++y) {
+    factor_slice(sm, G, y);
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      st(fac, fbase + (size_t)y * nn + e, cscale(cadd(sm.A[i][j], sm.A[j][i]), 0.5));
+      sm.Gp[i][j] = sm.A[i][j];
     }
     __syncthreads();
   }
-  if (!DIAG) return;
-  // backward selected inversion: Gc holds G_{y+1,y+1} in Gp
-  if (i < sx && j < sx) Gp[i][j] = Gall[sy - 1][i][j];
-  __syncthreads();
-  if (tid < sx) {
-    const int l = tid + sx * (sy - 1);
-    size_t p = (size_t)t * S + l;
-    if (G.kind[p] == 1) st(gdiag, (size_t)k * NP + p, Gp[tid][tid]);
-  }
-  for (int y = sy - 2; y >= 0; --y) {
-    // tmp = C M C G_y, C = diag(c_{y+1})
-    if (i < sx && j < sx) {
+  // Gp = G_{ns-1,ns-1}
+  auto write_diag = [&](int y) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const size_t p = (size_t)t * G.S + i + n * y;
+      if (G.kind[p] == 1) st(gdiag, (size_t)k * NP + p, sm.Gp[i][i]);
+    }
+  };
+  write_diag(ns - 1);
+  for (int y = ns - 2; y >= 0; --y) {
+    for (int e = threadIdx.x; e < nn; e += blockDim.x)
+      sm.A[e / n][e % n] = ld(fac, fbase + (size_t)y * nn + e);  // S_y^{-1}
+    __syncthreads();
+    // tmp = C M C S_y^{-1}, C = diag(bonds between slices y and y+1)
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int i = e / n, j = e % n;
       cd acc = cmk(0.0, 0.0);
-      const bool ci = act[i + sx * (y + 1)] && act[i + sx * y];
-      if (ci)
-        for (int l = 0; l < sx; ++l)
-          if (act[l + sx * (y + 1)] && act[l + sx * y]) acc = cfma(Gp[i][l], Gall[y][l][j], acc);
-      tmp[i][j] = acc;
+      if (sm.act[i + n * (y + 1)] && sm.act[i + n * y])
+        for (int l = 0; l < n; ++l)
+          if (sm.act[l + n * (y + 1)] && sm.act[l + n * y]) acc = cfma(sm.Gp[i][l], sm.A[l][j], acc);
+      sm.tmp[i][j] = acc;
     }
     __syncthreads();
-    cd nv = cmk(0.0, 0.0);
-    if (i < sx && j < sx) {
+    cd nv[6];
+    int c = 0;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) {
+      const int i = e / n, j = e % n;
       cd acc = cmk(0.0, 0.0);
-      for (int l = 0; l < sx; ++l) acc = cfma(Gall[y][i][l], tmp[l][j], acc);
-      nv = cadd(Gall[y][i][j], cscale(acc, tt * tt));
+      for (int l = 0; l < n; ++l) acc = cfma(sm.A[i][l], sm.tmp[l][j], acc);
+      nv[c] = cadd(sm.A[i][j], cscale(acc, tt * tt));
     }
     __syncthreads();
-    if (i < sx && j < sx) Gp[i][j] = nv;
+    c = 0;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) sm.Gp[e / n][e % n] = nv[c];
     __syncthreads();
-    if (tid < sx) {
-      const int l = tid + sx * y;
-      size_t p = (size_t)t * S + l;
-      if (G.kind[p] == 1) st(gdiag, (size_t)k * NP + p, Gp[tid][tid]);
-    }
+    write_diag(y);
+    __syncthreads();
   }
 }
 
@@ -227,27 +266,18 @@ __global__ __launch_bounds__(256) void k_lz_defect(LzArgs a, const double* __res
   LZ_ITEM();
   const TileGeom& G = a.G;
   const size_t kb = (size_t)k * NP;
-  const int tid = threadIdx.x, sx = G.sx;
+  const int tid = threadIdx.x;
   if (tid >= G.S) return;
   const size_t p = (size_t)t * G.S + tid;
   cd out = cmk(0.0, 0.0);
   if (G.kind[p] == 2 && G.depth[p] == a.level) {
     const int gB = a.level + 1;
-    const int lx = tid % sx, ly = tid / sx;
     cd acc = cmk(0.0, 0.0);
-    auto add = [&](int nt, int nl) {
+    for (int dir = 0; dir < 6; ++dir) {
+      int nt, nl;
+      if (!site_nbr(G, t, tid, dir, nt, nl)) continue;
       const size_t np = (size_t)nt * G.S + nl;
       if (active(G.kind[np], G.depth[np], gB)) acc = cadd(acc, ld(w, kb + np));
-    };
-    if (lx > 0) add(t, tid - 1);
-    else if (G.nbr[t * 4 + 0] >= 0) add(G.nbr[t * 4 + 0], tid + sx - 1);
-    if (lx < sx - 1) add(t, tid + 1);
-    else if (G.nbr[t * 4 + 1] >= 0) add(G.nbr[t * 4 + 1], tid - (sx - 1));
-    if (G.sy > 1) {
-      if (ly > 0) add(t, tid - sx);
-      else if (G.nbr[t * 4 + 2] >= 0) add(G.nbr[t * 4 + 2], tid + sx * (G.sy - 1));
-      if (ly < G.sy - 1) add(t, tid + sx);
-      else if (G.nbr[t * 4 + 3] >= 0) add(G.nbr[t * 4 + 3], tid - sx * (G.sy - 1));
     }
     out = csub(ld(q, kb + p), cscale(acc, G.t));
   }
@@ -301,8 +331,9 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   LZ_ITEM();
   const TileGeom& G = a.G;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[3], (unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
+  if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
+    a.wctr[(size_t)1 * a.n_items + item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
+                                            ((unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
   cd rl[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -346,8 +377,9 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
                                                     double* __restrict__ r, double* __restrict__ D) {
   LZ_ITEM();
   const TileGeom& G = a.G;
-  if (a.wctr && threadIdx.x == 0)
-    atomicAdd(&a.wctr[2], (unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec);
+  if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
+    a.wctr[item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
+                    ((unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec);
   __shared__ cd hl[1024];
   const double* hs = a.h + (size_t)item * a.hstride * 2;
   for (int i = threadIdx.x; i < nvec && i < 1024; i += blockDim.x) hl[i] = ld(hs, i);
@@ -494,15 +526,15 @@ void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const
   k_assemble<<<grid, 256, 0, s>>>(G, K, mu, V, omega, sigma, d);
 }
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
-                   void* fac, bool fp32, double* gdiag, hipStream_t s) {
+                   void* fac, bool fp32, bool fp16, hipStream_t s) {
   dim3 grid = tiles_grid(G, K);
-  if (gdiag) {
-    k_factor<double, true><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac, gdiag);
-  } else if (fp32) {
-    k_factor<float, false><<<grid, 256, 0, s>>>(G, g, tile_node, d, (float*)fac, nullptr);
-  } else {
-    k_factor<double, false><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac, nullptr);
-  }
+  if (fp16) k_factor<__half><<<grid, 256, 0, s>>>(G, g, tile_node, d, (__half*)fac);
+  else if (fp32) k_factor<float><<<grid, 256, 0, s>>>(G, g, tile_node, d, (float*)fac);
+  else k_factor<double><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac);
+}
+void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64, double* gdiag,
+                        hipStream_t s) {
+  k_factor_diag<<<tiles_grid(G, K), 256, 0, s>>>(G, d, fac64, gdiag);
 }
 
 void launch_count_open(const int* done, int n, int* out, hipStream_t s) {

@@ -1,7 +1,8 @@
 // Domain decomposition planner: Fig. 1 / eq. (4) (one level, every separator
 // at once) and the recursive variant at the end of Sec. II.C (one separator
 // plane per domain, through the longest axis, nearest its middle, which
-// alternates (d_x, d_y) = (2,1), (1,2), ... on square domains).
+// alternates (d_x, d_y) = (2,1), (1,2), ... on square domains; on cubes it
+// cycles x, y, z).
 #include "plan.h"
 
 #include <algorithm>
@@ -43,24 +44,27 @@ dyson_opts merge_opts(const dyson_opts* u) {
 
 namespace {
 
-struct Box {  // tile box [x0,x1) x [y0,y1)
-  int x0, x1, y0, y1;
+struct Box {  // tile box [lo[a], hi[a]) per axis
+  int lo[3], hi[3];
 };
 
 }  // namespace
 
 std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPlan& P) {
-  if (lat.dim != 1 && lat.dim != 2)
-    return "dim must be 1 or 2 (3-D lattices are not built in this library yet)";
+  if (lat.dim < 1 || lat.dim > 3) return "dim must be 1, 2 or 3";
   for (int a = 0; a < 3; ++a) {
     if (lat.L[a] < 1) return "lattice extents must be >= 1";
     if (a >= lat.dim && lat.L[a] != 1) return "unused lattice axes must have extent 1";
   }
   if (!std::isfinite(lat.t) || !std::isfinite(lat.mu)) return "t and mu must be finite";
-  if (opts.leaf_edge < 2 || opts.leaf_edge > 16) return "leaf_edge must be in [2, 16]";
+  const int smax = (lat.dim == 3) ? 6 : 16;
+  if (opts.leaf_edge < 2 || opts.leaf_edge > smax)
+    return lat.dim == 3 ? "leaf_edge must be in [2, 6] for cubic lattices"
+                        : "leaf_edge must be in [2, 16]";
   if (opts.partition != DYSON_PART_NESTED && opts.partition != DYSON_PART_SINGLE)
     return "unknown partition";
-  if (opts.precision != DYSON_PREC_FP64 && opts.precision != DYSON_PREC_MIXED)
+  if (opts.precision != DYSON_PREC_FP64 && opts.precision != DYSON_PREC_MIXED &&
+      opts.precision != DYSON_PREC_MIXED16)
     return "unknown precision";
   if (opts.max_rank < 0 || opts.extra_steps < 0) return "max_rank and extra_steps must be >= 0";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
@@ -73,89 +77,101 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   P.mu = lat.mu;
   P.opts = opts;
   P.s = opts.leaf_edge;
-  P.sx = P.s;
-  P.sy = (lat.dim == 2) ? P.s : 1;
+  const int s = P.s, D = lat.dim;
+  // block rows of the tile factorization: rows of s sites (chain, square) or
+  // planes of s^2 sites (cubic), stacked along the slowest axis
+  P.sx = (D == 3) ? s * s : s;
+  P.sy = (D == 1) ? 1 : s;
   P.S = P.sx * P.sy;
-  P.Tx = (P.L[0] + P.s - 1) / P.s;
-  P.Ty = (lat.dim == 2) ? (P.L[1] + P.s - 1) / P.s : 1;
-  P.T = P.Tx * P.Ty;
+  int TT[3] = {1, 1, 1};
+  for (int a = 0; a < D; ++a) TT[a] = (P.L[a] + s - 1) / s;
+  P.Tx = TT[0];
+  P.Ty = TT[1];
+  P.Tz = TT[2];
+  P.T = TT[0] * TT[1] * TT[2];
   P.N = (int)n;
-  const int s = P.s, Lx = P.L[0], Ly = P.L[1];
 
-  // site coordinate ranges of a tile box; the high fringe belongs to an
-  // ancestor separator unless the box reaches the lattice edge
-  auto xr = [&](const Box& b, int& lo, int& hi) {
-    lo = s * b.x0;
-    hi = (b.x1 < P.Tx) ? s * b.x1 - 1 : Lx;
-  };
-  auto yr = [&](const Box& b, int& lo, int& hi) {
-    if (P.dim == 1) { lo = 0; hi = 1; return; }
-    lo = s * b.y0;
-    hi = (b.y1 < P.Ty) ? s * b.y1 - 1 : Ly;
+  // site coordinate range of a tile box along axis a; the high fringe belongs
+  // to an ancestor separator unless the box reaches the lattice edge
+  auto range = [&](const Box& b, int a, int& lo, int& hi) {
+    if (a >= D) { lo = 0; hi = 1; return; }
+    lo = s * b.lo[a];
+    hi = (b.hi[a] < TT[a]) ? s * b.hi[a] - 1 : P.L[a];
   };
 
   struct Node {
     Box box;
     int level;
-    std::vector<int> split_x, split_y;  // tile boundaries i: separator line at s*i-1
+    std::vector<int> split[3];  // tile boundaries i: separator plane at s*i-1
     std::vector<int> children;
   };
   std::vector<Node> nodes;
   std::function<int(Box, int)> rec = [&](Box b, int level) -> int {
     int id = (int)nodes.size();
-    nodes.push_back(Node{b, level, {}, {}, {}});
-    std::vector<int> cx, cy;
-    for (int i = b.x0 + 1; i < b.x1; ++i) cx.push_back(i);
-    for (int i = b.y0 + 1; i < b.y1; ++i) cy.push_back(i);
-    if (cx.empty() && cy.empty()) return id;
-    std::vector<int> sxs, sys;
+    nodes.push_back(Node{b, level, {}, {}});
+    std::vector<int> cand[3];
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+      for (int i = b.lo[a] + 1; i < b.hi[a]; ++i) cand[a].push_back(i);
+      any |= !cand[a].empty();
+    }
+    if (!any) return id;
+    std::vector<int> sp[3];
     if (opts.partition == DYSON_PART_SINGLE) {
-      sxs = cx;
-      sys = cy;
+      for (int a = 0; a < 3; ++a) sp[a] = cand[a];
     } else {
-      int xlo, xhi, ylo, yhi;
-      xr(b, xlo, xhi);
-      yr(b, ylo, yhi);
-      int ex = cx.empty() ? -1 : xhi - xlo, ey = cy.empty() ? -1 : yhi - ylo;
-      bool along_x = ex >= ey;  // first longest axis
-      const std::vector<int>& c = along_x ? cx : cy;
-      double mid = along_x ? 0.5 * (xlo + xhi - 1) : 0.5 * (ylo + yhi - 1);
-      int best = c[0];
+      int best_axis = -1, best_ext = -1;
+      for (int a = 0; a < 3; ++a) {
+        if (cand[a].empty()) continue;
+        int lo, hi;
+        range(b, a, lo, hi);
+        if (hi - lo > best_ext) { best_ext = hi - lo; best_axis = a; }  // first longest axis
+      }
+      int lo, hi;
+      range(b, best_axis, lo, hi);
+      const double mid = 0.5 * (lo + hi - 1);
+      int best = cand[best_axis][0];
       double bd = std::fabs((s * best - 1) - mid);
-      for (int i : c) {
+      for (int i : cand[best_axis]) {
         double dd = std::fabs((s * i - 1) - mid);
         if (dd < bd) { bd = dd; best = i; }  // ties keep the lower plane
       }
-      (along_x ? sxs : sys).push_back(best);
+      sp[best_axis].push_back(best);
     }
-    nodes[id].split_x = sxs;
-    nodes[id].split_y = sys;
-    std::vector<int> bx{b.x0}, by{b.y0};
-    for (int i : sxs) bx.push_back(i);
-    bx.push_back(b.x1);
-    for (int i : sys) by.push_back(i);
-    by.push_back(b.y1);
+    for (int a = 0; a < 3; ++a) nodes[id].split[a] = sp[a];
+    std::vector<int> edges[3];
+    for (int a = 0; a < 3; ++a) {
+      edges[a].push_back(b.lo[a]);
+      for (int i : sp[a]) edges[a].push_back(i);
+      edges[a].push_back(b.hi[a]);
+    }
     std::vector<int> ch;
-    for (size_t yi = 0; yi + 1 < by.size(); ++yi)
-      for (size_t xi = 0; xi + 1 < bx.size(); ++xi)
-        ch.push_back(rec(Box{bx[xi], bx[xi + 1], by[yi], by[yi + 1]}, level + 1));
+    for (size_t zi = 0; zi + 1 < edges[2].size(); ++zi)
+      for (size_t yi = 0; yi + 1 < edges[1].size(); ++yi)
+        for (size_t xi = 0; xi + 1 < edges[0].size(); ++xi)
+          ch.push_back(rec(Box{{edges[0][xi], edges[1][yi], edges[2][zi]},
+                               {edges[0][xi + 1], edges[1][yi + 1], edges[2][zi + 1]}},
+                           level + 1));
     nodes[id].children = ch;
     return id;
   };
-  rec(Box{0, P.Tx, 0, P.Ty}, 0);
+  rec(Box{{0, 0, 0}, {TT[0], TT[1], TT[2]}}, 0);
 
   // depth-first tile order
+  auto gidx = [&](int gx, int gy, int gz) { return (gz * TT[1] + gy) * TT[0] + gx; };
   std::vector<int> tile_of_grid(P.T, -1);
   P.tile_gx.clear();
   P.tile_gy.clear();
+  P.tile_gz.clear();
   std::vector<int> first(nodes.size()), last(nodes.size());
   std::function<void(int)> dfs = [&](int id) {
     first[id] = (int)P.tile_gx.size();
     const Node& nd = nodes[id];
     if (nd.children.empty()) {
-      tile_of_grid[nd.box.y0 * P.Tx + nd.box.x0] = (int)P.tile_gx.size();
-      P.tile_gx.push_back(nd.box.x0);
-      P.tile_gy.push_back(nd.box.y0);
+      tile_of_grid[gidx(nd.box.lo[0], nd.box.lo[1], nd.box.lo[2])] = (int)P.tile_gx.size();
+      P.tile_gx.push_back(nd.box.lo[0]);
+      P.tile_gy.push_back(nd.box.lo[1]);
+      P.tile_gz.push_back(nd.box.lo[2]);
     } else {
       for (int c : nd.children) dfs(c);
     }
@@ -164,13 +180,16 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   dfs(0);
   if ((int)P.tile_gx.size() != P.T) return "internal: tile count mismatch";
 
-  P.nbr.assign(P.T * 4, -1);
+  P.nbr.assign(P.T * 6, -1);
   for (int t = 0; t < P.T; ++t) {
-    int gx = P.tile_gx[t], gy = P.tile_gy[t];
-    if (gx > 0) P.nbr[t * 4 + 0] = tile_of_grid[gy * P.Tx + gx - 1];
-    if (gx + 1 < P.Tx) P.nbr[t * 4 + 1] = tile_of_grid[gy * P.Tx + gx + 1];
-    if (gy > 0) P.nbr[t * 4 + 2] = tile_of_grid[(gy - 1) * P.Tx + gx];
-    if (gy + 1 < P.Ty) P.nbr[t * 4 + 3] = tile_of_grid[(gy + 1) * P.Tx + gx];
+    const int g[3] = {P.tile_gx[t], P.tile_gy[t], P.tile_gz[t]};
+    for (int a = 0; a < 3; ++a)
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        int h[3] = {g[0], g[1], g[2]};
+        h[a] += sgn ? 1 : -1;
+        if (h[a] < 0 || h[a] >= TT[a]) continue;
+        P.nbr[t * 6 + 2 * a + sgn] = tile_of_grid[gidx(h[0], h[1], h[2])];
+      }
   }
 
   // site maps
@@ -178,16 +197,22 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   P.depth.assign((size_t)P.T * P.S, 0);
   P.site_of.assign((size_t)P.T * P.S, -1);
   P.pos_of.assign(P.N, -1);
-  auto pos = [&](int x, int y) {
-    int t = tile_of_grid[(y / s) * P.Tx + (x / s)];
-    return (size_t)t * P.S + (x % s) + P.sx * (P.dim == 2 ? (y % s) : 0);
+  const int Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
+  auto pos = [&](int x, int y, int z) {
+    const int t = tile_of_grid[gidx(x / s, y / s, z / s)];
+    int l = x % s;
+    if (D >= 2) l += s * (y % s);
+    if (D == 3) l += s * s * (z % s);
+    return (size_t)t * P.S + l;
   };
-  for (int y = 0; y < Ly; ++y)
-    for (int x = 0; x < Lx; ++x) {
-      size_t p = pos(x, y);
-      P.site_of[p] = x + Lx * y;
-      P.pos_of[x + Lx * y] = (int)p;
-    }
+  for (int z = 0; z < Lz; ++z)
+    for (int y = 0; y < Ly; ++y)
+      for (int x = 0; x < Lx; ++x) {
+        const size_t p = pos(x, y, z);
+        const int i = x + Lx * (y + Ly * z);
+        P.site_of[p] = i;
+        P.pos_of[i] = (int)p;
+      }
 
   // separators top-down (a site takes the level of the first plane through
   // it), leaf sites take the depth of their leaf
@@ -203,37 +228,28 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   std::vector<char> claimed(P.N, 0);
   for (int id : order) {
     const Node& nd = nodes[id];
-    int xlo, xhi, ylo, yhi;
-    xr(nd.box, xlo, xhi);
-    yr(nd.box, ylo, yhi);
-    if (nd.children.empty()) {
-      for (int y = ylo; y < yhi; ++y)
-        for (int x = xlo; x < xhi; ++x) {
-          int i = x + Lx * y;
-          if (claimed[i]) continue;
-          claimed[i] = 1;
-          size_t p = P.pos_of[i];
-          P.kind[p] = KIND_LEAF;
-          P.depth[p] = (uint8_t)nd.level;
-        }
-      continue;
-    }
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) range(nd.box, a, lo[a], hi[a]);
+    const bool leaf = nd.children.empty();
     int m = 0;
-    for (int y = ylo; y < yhi; ++y)
-      for (int x = xlo; x < xhi; ++x) {
-        bool on = false;
-        for (int i : nd.split_x) on |= (x == s * i - 1);
-        for (int i : nd.split_y) on |= (y == s * i - 1);
-        int i = x + Lx * y;
-        if (!on || claimed[i]) continue;
-        claimed[i] = 1;
-        size_t p = P.pos_of[i];
-        P.kind[p] = KIND_SEP;
-        P.depth[p] = (uint8_t)nd.level;
-        ++m;
-      }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) {
+          const int c[3] = {x, y, z};
+          bool on = false;
+          for (int a = 0; a < 3 && !leaf; ++a)
+            for (int i : nd.split[a]) on |= (c[a] == s * i - 1);
+          const int i = x + Lx * (y + Ly * z);
+          if ((!leaf && !on) || claimed[i]) continue;
+          claimed[i] = 1;
+          const size_t p = P.pos_of[i];
+          P.kind[p] = leaf ? KIND_LEAF : KIND_SEP;
+          P.depth[p] = (uint8_t)nd.level;
+          ++m;
+        }
+    if (leaf) continue;
     LevelTable& lv = P.levels[nd.level];
-    int idx = lv.n_nodes++;
+    const int idx = lv.n_nodes++;
     lv.tile_lo.push_back(first[id]);
     lv.tile_hi.push_back(last[id]);
     lv.m.push_back(m);

@@ -31,12 +31,13 @@ struct HostPlan {
   double t = -1.0, mu = 0.0;
   dyson_opts opts{};
   int s = 16;         // leaf edge
-  int sx = 16, sy = 16;
-  int S = 256;        // padded sites per tile (sx*sy)
-  int Tx = 1, Ty = 1, T = 1;
+  int sx = 16, sy = 16;  // block rows of a tile: sy slices of sx sites
+                         // (rows of s sites; planes of s*s sites on cubes)
+  int S = 256;        // padded sites per tile (sx*sy = s^dim)
+  int Tx = 1, Ty = 1, Tz = 1, T = 1;
   int N = 1;
-  std::vector<int> tile_gx, tile_gy;  // grid coordinates of tile t
-  std::vector<int> nbr;               // [T*4]: -x, +x, -y, +y neighbour tile or -1
+  std::vector<int> tile_gx, tile_gy, tile_gz;  // grid coordinates of tile t
+  std::vector<int> nbr;  // [T*6]: -x, +x, -y, +y, -z, +z neighbour tile or -1
   std::vector<uint8_t> kind, depth;   // [T*S] tile-major
   std::vector<int> site_of;           // [T*S] natural site index or -1 (padding)
   std::vector<int> pos_of;            // [N] tile-major position of natural site

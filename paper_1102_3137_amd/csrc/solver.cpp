@@ -110,6 +110,7 @@ struct dyson_plan {
   double *d = nullptr, *gacc = nullptr, *xB = nullptr, *xH = nullptr, *r = nullptr, *z = nullptr,
          *p0 = nullptr, *p1 = nullptr, *s = nullptr, *rhs = nullptr, *R = nullptr, *Q = nullptr;
   void* fac[2] = {nullptr, nullptr};
+  double* fac64 = nullptr;  // complex128 leaf factors written with the leaf diagonal
   int fac_g[2] = {-1000, -1000};
   double* partial = nullptr;
   double *hpart = nullptr, *h = nullptr;
@@ -125,6 +126,8 @@ struct dyson_plan {
   std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
   int* h_count = nullptr;  // pinned
   unsigned long long* d_prof = nullptr;
+  unsigned long long* d_wprof = nullptr;  // [4][K*nmax] per-item byte counts (profiling):
+                                          // inner solves in [0,2), Lanczos in [2,4)
   uint64_t* d_fkey = nullptr;
   Prof prof;
   // run statistics of the current call
@@ -185,8 +188,19 @@ dyson_status ensure_workspace(dyson_plan* p, int K) {
   CHECKED(walloc(p, &p->Q, V * (size_t)nq));
   const size_t fe = (size_t)K * P.T * P.sy * P.sx * P.sx * 2;  // reals per factor set
   for (int i = 0; i < 2; ++i) {
+    if (P.opts.precision == DYSON_PREC_FP64) {
+      double* f;
+      CHECKED(walloc(p, &f, fe));
+      p->fac[i] = f;
+      if (i == 0) p->fac64 = f;  // the leaf factors are the deepest B preconditioner
+      continue;
+    }
     if (P.opts.precision == DYSON_PREC_MIXED) {
       float* f;
+      CHECKED(walloc(p, &f, fe));
+      p->fac[i] = f;
+    } else if (P.opts.precision == DYSON_PREC_MIXED16) {
+      uint16_t* f;
       CHECKED(walloc(p, &f, fe));
       p->fac[i] = f;
     } else {
@@ -195,6 +209,7 @@ dyson_status ensure_workspace(dyson_plan* p, int K) {
       p->fac[i] = f;
     }
   }
+  if (P.opts.precision != DYSON_PREC_FP64) CHECKED(walloc(p, &p->fac64, fe));
   CHECKED(walloc(p, &p->partial, (size_t)K * P.T * 4));
   CHECKED(walloc(p, &p->hpart, (size_t)K * P.T * p->hstride * 2));
   const size_t ni = (size_t)K * p->nmax;
@@ -213,6 +228,8 @@ dyson_status ensure_workspace(dyson_plan* p, int K) {
   CHECKED(walloc(p, &p->lz_scal, ni * 2));
   CHECKED(walloc(p, &p->d_count, 4));
   CHECKED(walloc(p, &p->d_prof, 8));
+  CHECKED(walloc(p, &p->d_wprof, 4 * ni));
+  HIPC(hipMemset(p->d_wprof, 0, 4 * ni * sizeof(unsigned long long)));
   CHECKED(walloc(p, &p->d_fkey, (size_t)K));
   HIPC(hipHostMalloc((void**)&p->h_count, 4 * sizeof(int), hipHostMallocDefault));
   p->Kcap = K;
@@ -268,7 +285,8 @@ struct Run {
     int slot = (p->fac_g[0] == g + 1 || p->fac_g[0] == g - 1) ? 1 : 0;
     (void)level;  // every tile is factored: a graph is shared by two levels
     launch_factor(p->geom, K, g, nullptr, p->d, p->fac[slot],
-                  P().opts.precision == DYSON_PREC_MIXED, nullptr, s);
+                  P().opts.precision == DYSON_PREC_MIXED, P().opts.precision == DYSON_PREC_MIXED16,
+                  s);
     HIPC(hipGetLastError());
     p->fac_g[slot] = g;
     *fac = p->fac[slot];
@@ -298,7 +316,8 @@ struct Run {
     c.s = p->s;
     c.fac = fac;
     c.fp32 = HP.opts.precision == DYSON_PREC_MIXED;
-    c.wctr = p->prof.on ? p->d_prof : nullptr;
+    c.fp16 = HP.opts.precision == DYSON_PREC_MIXED16;
+    c.wctr = p->prof.on ? p->d_wprof : nullptr;
     c.tlo = L.tlo;
     c.thi = L.thi;
     c.n_items = K * L.n;
@@ -332,6 +351,7 @@ struct Run {
       p->pending = DYSON_ENOCONV;
       g_err = "inner COCG solve hit max_inner_iters";
     }
+    if (p->prof.on) launch_prof_collect(p->d_wprof, K * L.n, 2, 0, p->d_prof, s);
     p->pred[slot] = it;
     p->stat_inner += it;
     p->stat_inner_max = std::max(p->stat_inner_max, it);
@@ -357,7 +377,10 @@ struct Run {
     a.hpart = p->hpart;
     a.h = p->h;
     a.hstride = p->hstride;
-    a.wctr = p->prof.on ? p->d_prof : nullptr;
+    a.tlo = p->lv[level].tlo;
+    a.thi = p->lv[level].thi;
+    a.n_items = K * p->lv[level].n;
+    a.wctr = p->prof.on ? p->d_wprof + 2 * (size_t)K * p->nmax : nullptr;
     return a;
   }
 
@@ -453,6 +476,7 @@ struct Run {
       launch_lz_reopen(a, K, p->Dl, s);
       HIPC(hipGetLastError());
     }
+    if (p->prof.on) launch_prof_collect(a.wctr, n_items, 2, 2, p->d_prof, s);
     launch_add_into(a, K, p->Dl, p->gacc, s);
     HIPC(hipGetLastError());
     if (steps_out) *steps_out = st;
@@ -534,7 +558,7 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
       p->lv.push_back(d);
     }
     p->geom = TileGeom{P.T, P.S, P.sx, P.sy, P.N, P.t, p->d_nbr, p->d_kind, p->d_depth,
-                       p->d_site_of, p->d_pos_of};
+                       p->d_site_of, p->d_pos_of, P.s, P.dim};
   }
   *out = p.release();
   return DYSON_OK;
@@ -597,10 +621,13 @@ dyson_status dyson_footprint(const dyson_plan* p, int K, size_t* bytes) {
   const HostPlan& P = p->hp;
   const size_t NP = (size_t)P.T * P.S;
   const size_t V = (size_t)K * NP * 16;
-  const size_t fsz = (P.opts.precision == DYSON_PREC_MIXED) ? 8 : 16;
+  const size_t fsz = (P.opts.precision == DYSON_PREC_MIXED)   ? 8
+                     : (P.opts.precision == DYSON_PREC_MIXED16) ? 4
+                                                                : 16;
   const size_t nq = P.levels.empty() ? 1 : (size_t)(p->kcap + 1);
   size_t b = V * (12 + nq);
   b += 2 * (size_t)K * P.T * P.sy * P.sx * P.sx * fsz;
+  if (P.opts.precision != DYSON_PREC_FP64) b += (size_t)K * P.T * P.sy * P.sx * P.sx * 16;
   b += (size_t)K * P.T * 2 * 16 + (size_t)K * P.T * p->hstride * 16;
   b += (size_t)K * p->nmax * p->hstride * 16 + (size_t)K * p->nmax * 200;
   *bytes = b;
@@ -666,7 +693,7 @@ dyson_status dyson_leaf_diag(dyson_plan* p, int K, const double* d_d, double* d_
   launch_to_tile(p->geom, K, d_d, p->d, 1.0, s);
   const size_t V = (size_t)K * p->hp.T * p->hp.S * 2;
   HIPC(hipMemsetAsync(p->gacc, 0, V * sizeof(double), s));
-  launch_factor(p->geom, K, 255, nullptr, p->d, nullptr, false, p->gacc, s);
+  launch_factor_diag(p->geom, K, p->d, p->fac64, p->gacc, s);
   launch_from_tile(p->geom, K, p->gacc, d_Gleaf, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
@@ -728,7 +755,7 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
   // FP64 plans keep the leaf factors (FP64 buffers); mixed plans only take the
   // diagonal here and factor the preconditioner again in complex64
   const bool keep = P.opts.precision == DYSON_PREC_FP64;
-  launch_factor(p->geom, K, 255, nullptr, p->d, keep ? p->fac[0] : nullptr, false, p->gacc, s);
+  launch_factor_diag(p->geom, K, p->d, p->fac64, p->gacc, s);
   HIPC(hipGetLastError());
   if (keep && !P.levels.empty()) {
     // the leaf factors double as the preconditioner of the deepest B graph

@@ -41,7 +41,8 @@ def test_assemble_eq1():
     assert oracle.rel_err(d, ref) <= 1e-15
 
 
-@pytest.mark.parametrize("dims,s", [((32, 32), 16), ((37, 29), 8), ((5, 5), 3), ((40,), 8), ((16, 16), 16)])
+@pytest.mark.parametrize("dims,s", [((32, 32), 16), ((37, 29), 8), ((5, 5), 3), ((40,), 8), ((16, 16), 16),
+                                    ((9, 8, 7), 4), ((12, 12, 12), 6)])
 def test_leaf_diag(dims, s):
     w = _case(dims, K=2)
     V, om, sig, tV, tom, tsig = device_inputs(w)
@@ -88,7 +89,8 @@ def _dense_X_apply(w, d_row, p, level, q):
 
 
 @pytest.mark.parametrize("dims,s,part", [((32, 32), 16, 0), ((32, 32), 16, 1), ((37, 29), 8, 0),
-                                         ((5, 5), 3, 1), ((40,), 8, 0)])
+                                         ((5, 5), 3, 1), ((40,), 8, 0), ((9, 8, 7), 4, 0),
+                                         ((11, 9, 7), 4, 1)])
 def test_xmatvec(dims, s, part):
     w = _case(dims, K=2)
     V, om, sig, tV, tom, tsig = device_inputs(w)
@@ -105,7 +107,7 @@ def test_xmatvec(dims, s, part):
             assert np.max(np.abs(u[k] - ref)) <= 1e-10 * np.max(np.abs(ref)), (level, k)
 
 
-@pytest.mark.parametrize("dims,s,part", [((32, 32), 16, 1), ((37, 29), 8, 0)])
+@pytest.mark.parametrize("dims,s,part", [((32, 32), 16, 1), ((37, 29), 8, 0), ((9, 8, 7), 4, 0)])
 def test_correct_level_matches_dense_diag_X(dims, s, part):
     """One level of bilinear Lanczos with the streaming diagonal: the added
     diag(Q T Q^T) equals diag(X) of every domain of the level."""
@@ -160,11 +162,14 @@ SOLVE_CASES = [
     (_case((40,), K=2), 8, 0),                   # chain
     (_case((16, 16), K=2), 16, 0),               # a single leaf: no correction level
     (_case((48, 33), K=4, beta=20.0), 16, 0),    # more frequencies, uneven halves
+    (_case((9, 8, 7), K=2, mu=1.0), 4, 0),       # cubic lattice (Z = 6), ragged tiles
+    (_case((11, 9, 7), K=2, mu=1.0), 4, 1),      # cubic, one level
+    (_case((12, 12, 12), K=3, mu=1.0, beta=10.0), 6, 0),  # cubic, 6^3 tiles
 ]
 
 
 @pytest.mark.parametrize("w,s,part", SOLVE_CASES, ids=[f"{c[0].dims}-s{c[1]}-p{c[2]}" for c in SOLVE_CASES])
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "mixed", "mixed16"])
 def test_solve_full_rank(w, s, part, prec):
     V, om, sig, tV, tom, tsig = device_inputs(w)
     p = _plan(w, s, part, prec)
@@ -217,7 +222,7 @@ def test_invalid_inputs_rejected():
 
 
 @pytest.mark.parametrize("L,freqs,prec", [(128, (0, 1, 31, 63), 1), (128, (0, 63), 0),
-                                          (256, (0, 63), 1)])
+                                          (128, (0, 63), 2), (256, (0, 63), 1)])
 def test_solve_large_lattice(L, freqs, prec):
     """Recursive bisection with 16x16 tiles at 128^2 (6 levels) and 256^2
     (8 levels, the throughput workload's lattice) on the hardest and easiest
@@ -232,3 +237,20 @@ def test_solve_large_lattice(L, freqs, prec):
     print(f"{L}^2 freqs={freqs} prec={prec} err={err:.2e} rep={rep}")
     assert rep["truncated"] == 0
     assert err < (1e-9 if L >= 256 else 5e-10)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_solve_cubic_24(prec):
+    """24^3 simple cubic lattice (Z = 6, 6^3 tiles, top interface 576 sites) on
+    the hardest and easiest Matsubara frequencies at beta = 10, against the
+    block-tridiagonal oracle over z-planes."""
+    w = synth.Workload(dims=(24, 24, 24), t=-1.0, mu=1.0, vc=1e-3 * (48.0 / 24) ** 2, beta=10.0,
+                       freq_index=(0, 31), seed=3, name="cubic 24")
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    p = _plan(w, 6, 0, prec)
+    G, rep = p.solve(tV, tom, tsig, report=True)
+    ref = oracle_G(w, V, om, sig, method="rgf")
+    err = oracle.rel_err(G.cpu().numpy(), ref)
+    print(f"24^3 prec={prec} err={err:.2e} rep={rep}")
+    assert rep["truncated"] == 0
+    assert err < 1e-9

@@ -32,6 +32,8 @@ def test_library_exports_every_declared_symbol():
 def _host_plan(dims, s, part, **kw):
     lat = B.Lattice()
     lat.dim = len(dims)
+    if len(dims) > 3:
+        raise B.DysonError(1, "at most three axes")
     for a in range(3):
         lat.L[a] = dims[a] if a < len(dims) else 1
     lat.t, lat.mu = -1.0, 0.5
@@ -67,7 +69,8 @@ def _oracle_maps(dims, s, part):
 CASES = [((32, 32), 16, B.PART_SINGLE), ((32, 32), 16, B.PART_NESTED), ((5, 5), 3, B.PART_SINGLE),
          ((37, 29), 8, B.PART_NESTED), ((37, 29), 5, B.PART_SINGLE), ((40,), 8, B.PART_NESTED),
          ((16, 16), 16, B.PART_NESTED), ((17, 3), 16, B.PART_NESTED), ((64, 48), 16, B.PART_NESTED),
-         ((256, 256), 16, B.PART_NESTED)]
+         ((256, 256), 16, B.PART_NESTED), ((12, 12, 12), 6, B.PART_NESTED),
+         ((11, 9, 7), 4, B.PART_SINGLE), ((13, 10, 9), 4, B.PART_NESTED), ((24, 24, 24), 6, B.PART_NESTED)]
 
 
 @pytest.mark.parametrize("dims,s,part", CASES)
@@ -109,7 +112,8 @@ def test_fig1_single_level():
     assert info.levels == 1 and info.n_nodes[0] == 1 and info.max_m[0] == 9 and info.n_tiles == 4
 
 
-@pytest.mark.parametrize("dims,s", [((4, 4, 4), 4), ((8, 8), 1), ((8, 8), 17), ((0, 8), 4)])
+@pytest.mark.parametrize("dims,s", [((4, 4, 4), 7), ((8, 8), 1), ((8, 8), 17), ((0, 8), 4),
+                                    ((4, 4, 4, 4), 2)])
 def test_planner_rejects_invalid(dims, s):
     with pytest.raises(B.DysonError) as e:
         _host_plan(dims, s, B.PART_NESTED)
