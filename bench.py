@@ -89,6 +89,127 @@ def cpu_baseline(w, n_freq_sample, max_seconds=30.0):
                        f"lattice, O2 recursive Green's function, FP64, {dt:.1f} s"), results
 
 
+def serve_bench(args):
+    """Replays a seeded Poisson stream of solve requests (lattice, K, beta and
+    self-energy drawn per request) through the request server, inputs resident
+    on the device, and compares with the same requests solved one after the
+    other by the blocking call."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1102_3137_amd import Context, PART_NESTED, PREC_MIXED16, PREC_MIXED
+
+    prec = {"mixed": PREC_MIXED, "mixed16": PREC_MIXED16, "fp64": 0}[args.precision]
+    if args.serve_mix == "reduced":
+        trace = synth.serving_trace(args.serve_n, args.serve_rate, squares=(64, 128, 256),
+                                    cubes=(16, 24), k_range=(4, 16))
+    else:
+        trace = synth.serving_trace(args.serve_n, args.serve_rate)
+    dev = torch.device("cuda:0")
+    reqs = []
+    for t_arr, w in trace:
+        V, om, sig = synth.make_inputs(w)
+        reqs.append(dict(t=t_arr, w=w, V=torch.from_numpy(V).to(dev),
+                         om=torch.from_numpy(om).to(dev),
+                         sig=torch.from_numpy(np.ascontiguousarray(sig)).to(dev)))
+    torch.cuda.synchronize()
+    work = sum(r["w"].n_sites * r["w"].n_freq for r in reqs)
+
+    def plan_kw(w):
+        return dict(t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
+                    partition=PART_NESTED, precision=prec)
+
+    # one after the other, blocking calls (plans made before the clock starts)
+    ctx0 = Context(0)
+    plans0 = {}
+    for r in reqs:
+        if r["w"].dims not in plans0:
+            plans0[r["w"].dims] = ctx0.plan(r["w"].dims, **plan_kw(r["w"]))
+    t0 = time.perf_counter()
+    seq_lat = []
+    for r in reqs:
+        ts = time.perf_counter()
+        r["G_alone"] = plans0[r["w"].dims].solve(r["V"], r["om"], r["sig"])
+        torch.cuda.synchronize()
+        seq_lat.append(time.perf_counter() - ts)
+        log(f"sequential {len(seq_lat)}/{len(reqs)}: {r['w'].name}: {seq_lat[-1]:.2f} s")
+    t_seq = time.perf_counter() - t0
+    ctx0.close()
+    log(f"sequential: {len(reqs)} requests, {t_seq:.2f} s")
+
+    # served: arrivals replayed in real time on a submitting thread
+    ctx = Context(0, slots=args.serve_slots)
+    plans = {}
+    for r in reqs:
+        if r["w"].dims not in plans:
+            plans[r["w"].dims] = ctx.plan(r["w"].dims, **plan_kw(r["w"]))
+    handles = [None] * len(reqs)
+
+    def submitter(start):
+        for i, r in enumerate(reqs):
+            delay = start + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            handles[i] = plans[r["w"].dims].submit(r["V"], r["om"], r["sig"])
+
+    start = time.perf_counter()
+    th = threading.Thread(target=submitter, args=(start,))
+    th.start()
+    th.join()
+    lat, qwait, batches, mismatch = [], [], [], 0
+    for i, h in enumerate(handles):
+        G = h.wait()
+        rep = h.report()
+        log(f"served {i + 1}/{len(reqs)}: {reqs[i]['w'].name}: latency "
+            f"{rep['t_total_ms'] / 1000:.2f} s, queued {rep['t_queue_ms'] / 1000:.2f} s, "
+            f"{rep['batches']} batch(es)")
+        lat.append(rep["t_total_ms"] / 1000.0)
+        qwait.append(rep["t_queue_ms"] / 1000.0)
+        batches.append(rep["batches"])
+        mismatch += int(not torch.equal(G, reqs[i]["G_alone"]))
+    t_serve = time.perf_counter() - start
+    for h in handles:
+        h.release()
+    ctx.close()
+    log(f"served: {t_serve:.2f} s, mismatches vs alone: {mismatch}")
+
+    # accuracy of a sample against the oracle (smallest lattice, two frequencies)
+    import oracle
+    small = min(range(len(reqs)), key=lambda i: reqs[i]["w"].n_sites)
+    w = reqs[small]["w"]
+    V, om, sig = synth.make_inputs(w)
+    d = oracle.assemble_diag(V, om, sig, w.mu)[[0, w.n_freq - 1]]
+    ref = oracle.oracle_diag(w.dims, d, w.t)
+    Gs = reqs[small]["G_alone"].cpu().numpy()[[0, w.n_freq - 1]]
+    err = oracle.rel_err(Gs, ref)
+    log(f"oracle check on request {small} ({w.name}): {err:.3e}")
+
+    q = lambda a, f: float(np.quantile(np.array(a), f))  # noqa: E731
+    out = {
+        "metric": "served G_ii sites*freqs/sec at rel err <= 1e-6 vs FP64 oracle; "
+                  "p50/p99 request latency",
+        "value": work / t_serve if err <= 1e-6 else 0.0, "unit": "site*freq/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"Poisson stream, {len(reqs)} requests at {args.serve_rate}/s, "
+                               f"{args.serve_mix} lattice mix", "slots": args.serve_slots,
+                   "lattices": sorted({str(r['w'].dims) for r in reqs}),
+                   "k_per_request": [r["w"].n_freq for r in reqs]},
+        "latency_s": {"p50": q(lat, 0.5), "p99": q(lat, 0.99), "max": max(lat)},
+        "queue_wait_s": {"p50": q(qwait, 0.5), "p99": q(qwait, 0.99)},
+        "batches_per_request": {"mean": float(np.mean(batches)), "max": int(max(batches))},
+        "sequential_blocking": {"value": work / t_seq, "seconds": t_seq,
+                                "latency_s_p50": q(seq_lat, 0.5)},
+        "served_seconds": t_serve,
+        "speedup_vs_sequential": t_seq / t_serve,
+        "mismatches_vs_alone": mismatch,
+        "max_rel_err_sampled": err,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +225,15 @@ def main():
                     help="also time the plain per-frequency FP64 solve on 4 sampled frequencies")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: replay a seeded Poisson stream of requests through "
+                         "dyson_submit and print its throughput and p50/p99 latency instead")
+    ap.add_argument("--serve-n", type=int, default=12)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--serve-mix", choices=["reduced", "full"], default="reduced",
+                    help="reduced: squares 64/128/256, cubes 16/24, K in [4, 16]; "
+                         "full: squares 128/256/512, cubes 32/64, K in [16, 256]")
+    ap.add_argument("--serve-slots", type=int, default=3)
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -118,6 +248,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch

@@ -14,8 +14,10 @@
  *     element (k, i) of a [K][N] array sits at doubles 2*(k*N+i), 2*(k*N+i)+1.
  *   - Pointers named d_* are DEVICE pointers (hipMalloc'ed or any device
  *     memory visible to the plan's device); h_* are host pointers.
- *   - The caller owns every buffer passed in; the library never frees or
- *     keeps them beyond the call.  The library owns contexts and plans.
+ *   - The caller owns every buffer passed in; the library never frees them
+ *     and keeps none beyond the call, except the device buffers of a request
+ *     submitted with DYSON_MEM_DEVICE (borrowed until it is finished or
+ *     released).  The library owns contexts, plans and request handles.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
  *     stream-ordered; a call returns after its work is enqueued and, for
  *     the solve entry points, after it has completed (they poll device-side
@@ -45,7 +47,10 @@ typedef enum {
   DYSON_EBREAKDOWN = 3,  /* Lanczos breakdown not cured by restarts */
   DYSON_ENOCONV = 4,     /* an inner solve hit its iteration cap */
   DYSON_EDEVICE = 5,     /* HIP runtime error */
-  DYSON_EUNSUPPORTED = 6 /* valid request this build does not implement */
+  DYSON_EUNSUPPORTED = 6,/* valid request this build does not implement */
+  DYSON_EBUSY = 7,       /* object still in use (a plan with live requests) */
+  DYSON_ECANCELLED = 8,  /* the request was cancelled */
+  DYSON_ETIMEOUT = 9     /* dyson_wait returned before the request finished */
 } dyson_status;
 
 /* Lattice geometry and hopping (eq. (1)): chain, square (Z=4) or simple
@@ -104,6 +109,11 @@ typedef struct {
   double kern_ms[4];
   long long kern_launches[4];
   double kern_bytes[4];     /* algorithmic HBM bytes those launches moved */
+  /* served requests (dyson_req_report): t_total_ms is arrival -> completion */
+  double t_queue_ms;        /* arrival -> first frequency on the device */
+  int batches;              /* device batches the request's frequencies ran in */
+  size_t hbm_bytes;         /* largest workspace (device bytes) of those batches,
+                               or of the call for dyson_solve */
 } dyson_report;
 
 typedef struct dyson_ctx dyson_ctx;
@@ -120,14 +130,30 @@ typedef struct {
   long long sum_m[32];/* sum of m over the level's domains */
 } dyson_plan_info;
 
-/* Context on one HIP device.  device = ordinal. */
-dyson_status dyson_create(dyson_ctx** ctx, int device);
+/* Optional device allocator.  alloc returns device memory of `bytes` bytes
+ * usable on `stream` (NULL on failure); free releases it.  Both may be called
+ * from the library's worker threads. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} dyson_allocator;
+
+/* Context on one HIP device.  device = ordinal.  hbm_budget = device bytes
+ * the serving slots may hold at once (0 = 90% of the device memory free at
+ * creation); blocking calls allocate outside it.  allocator = NULL uses
+ * hipMalloc/hipFree.  dyson_destroy stops the server: frequencies still
+ * queued are dropped (their requests end with DYSON_ECANCELLED), batches on
+ * the device finish first.  Request handles stay valid until released. */
+dyson_status dyson_create(dyson_ctx** ctx, int device, size_t hbm_budget,
+                          const dyson_allocator* allocator);
 dyson_status dyson_destroy(dyson_ctx* ctx);
 
 /* Build the domain decomposition (host only, integer work; Fig. 1, eq. (4),
  * recursion at the end of Sec. II.C).  opts may be NULL for defaults. */
 dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat,
                                const dyson_opts* opts, dyson_plan** plan);
+/* DYSON_EBUSY while requests submitted on the plan are not yet released. */
 dyson_status dyson_plan_destroy(dyson_plan* plan);
 dyson_status dyson_plan_get_info(const dyson_plan* plan, dyson_plan_info* info);
 
@@ -140,7 +166,8 @@ dyson_status dyson_plan_get_info(const dyson_plan* plan, dyson_plan_info* info);
 dyson_status dyson_plan_get_maps(const dyson_plan* plan, int* h_depth,
                                  int* h_is_sep, int* h_tile);
 
-/* Device memory a dyson_solve over K frequencies will allocate (bytes). */
+/* Device memory a dyson_solve over K frequencies will allocate (bytes); the
+ * serving slots hold the same per batch of K frequencies. */
 dyson_status dyson_footprint(const dyson_plan* plan, int K, size_t* bytes);
 
 /* Full hot path: diag(H(i w_k)^{-1}) for K frequencies.
@@ -184,6 +211,48 @@ dyson_status dyson_xmatvec(dyson_plan* plan, int level, int K,
 dyson_status dyson_correct_level(dyson_plan* plan, int level, int K,
                                  const double* d_d, double* d_Gacc,
                                  int* h_steps, void* stream);
+
+/* ---- Serving: asynchronous requests with continuous batching ----
+ * A request is one dyson_solve's worth of work (eq. (1) inputs for K
+ * frequencies of one plan).  Requests are cut into runs of frequencies
+ * (frequencies are independent problems); a pool of slots, each with its own
+ * HIP stream and workspace, takes the oldest waiting frequencies together
+ * with those of every other waiting request on the same plan, up to
+ * max_batch_freqs and as far as the HBM budget allows, and runs them as one
+ * batch.  Requests that arrive while batches run join the next batch a slot
+ * forms; slots run concurrently on the device.  Results do not depend on how
+ * requests were batched: every (domain, frequency) item is computed the
+ * same way alone or in a mix (its start vector is keyed by the bits of w_k).
+ *
+ * mem = DYSON_MEM_DEVICE: V, omega, sigma and G are device pointers that the
+ * library borrows until the request is finished or released; inputs must be
+ * complete (stream-synchronized) when dyson_submit is called.
+ * mem = DYSON_MEM_HOST: V, omega, sigma are host arrays copied before
+ * dyson_submit returns; G is a host array written when the request finishes.
+ * Inputs are validated in dyson_submit (DYSON_EINVAL, as for dyson_solve).
+ * The first dyson_submit on a context starts its server. */
+enum { DYSON_MEM_DEVICE = 0, DYSON_MEM_HOST = 1 };
+typedef struct dyson_req dyson_req;
+
+/* Slots (1..8, default 3) and frequencies per batch (1..4096, default 256);
+ * call before the first dyson_submit on the context. */
+dyson_status dyson_serve_config(dyson_ctx* ctx, int slots, int max_batch_freqs);
+dyson_status dyson_submit(dyson_plan* plan, int K, const double* V, const double* omega,
+                          const double* sigma, double* G, int mem, dyson_req** req);
+/* *done = 1 once the request has finished (successfully or not). */
+dyson_status dyson_poll(dyson_req* req, int* done);
+/* Block until the request finishes or timeout_s (< 0: no limit) passes.
+ * Returns the request's final status, or DYSON_ETIMEOUT. */
+dyson_status dyson_wait(dyson_req* req, double timeout_s);
+/* Drop the request's frequencies that are still queued; those already on
+ * the device finish.  The request ends with DYSON_ECANCELLED and G is
+ * unspecified.  No effect on a finished request. */
+dyson_status dyson_cancel(dyson_req* req);
+/* Timing and statistics of a finished request (DYSON_EBUSY before). */
+dyson_status dyson_req_report(dyson_req* req, dyson_report* report);
+/* Cancel if unfinished, wait until none of its frequencies is on the device,
+ * and free the handle. */
+dyson_status dyson_release(dyson_req* req);
 
 const char* dyson_last_error(void);
 const char* dyson_version(void);

@@ -5,8 +5,10 @@ The compute path is the HIP library libdyson_mi355x.so (C ABI in
 include/dyson.h); `binding` marshals arguments to it.  There is no CPU
 fallback: loading fails loudly when the library is missing.
 """
-from .binding import (DysonError, Lattice, Opts, Report, PlanInfo, Plan, load_library,
-                      PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED, PREC_MIXED16)
+from .binding import (DysonError, Lattice, Opts, Report, PlanInfo, Plan, Context, Request,
+                      Allocator, load_library, PART_NESTED, PART_SINGLE, PREC_FP64, PREC_MIXED,
+                      PREC_MIXED16, MEM_DEVICE, MEM_HOST)
 
-__all__ = ["DysonError", "Lattice", "Opts", "Report", "PlanInfo", "Plan", "load_library",
-           "PART_NESTED", "PART_SINGLE", "PREC_FP64", "PREC_MIXED", "PREC_MIXED16"]
+__all__ = ["DysonError", "Lattice", "Opts", "Report", "PlanInfo", "Plan", "Context", "Request",
+           "Allocator", "load_library", "PART_NESTED", "PART_SINGLE", "PREC_FP64", "PREC_MIXED",
+           "PREC_MIXED16", "MEM_DEVICE", "MEM_HOST"]

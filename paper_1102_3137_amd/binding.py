@@ -15,8 +15,12 @@ LIB_PATH = os.path.join(HERE, "libdyson_mi355x.so")
 
 PART_NESTED, PART_SINGLE = 0, 1
 PREC_FP64, PREC_MIXED, PREC_MIXED16 = 0, 1, 2
+MEM_DEVICE, MEM_HOST = 0, 1
 STATUS = {0: "DYSON_OK", 1: "DYSON_EINVAL", 2: "DYSON_ENOMEM", 3: "DYSON_EBREAKDOWN",
-          4: "DYSON_ENOCONV", 5: "DYSON_EDEVICE", 6: "DYSON_EUNSUPPORTED"}
+          4: "DYSON_ENOCONV", 5: "DYSON_EDEVICE", 6: "DYSON_EUNSUPPORTED", 7: "DYSON_EBUSY",
+          8: "DYSON_ECANCELLED", 9: "DYSON_ETIMEOUT"}
+OK, EINVAL, ENOMEM, EBREAKDOWN, ENOCONV, EDEVICE, EUNSUPPORTED, EBUSY, ECANCELLED, ETIMEOUT = \
+    range(10)
 
 
 class DysonError(RuntimeError):
@@ -41,7 +45,8 @@ class Report(C.Structure):
                 ("lanczos_steps", C.c_longlong), ("inner_iters", C.c_longlong),
                 ("inner_iters_max", C.c_int), ("restarts", C.c_int), ("truncated", C.c_int),
                 ("kern_ms", C.c_double * 4), ("kern_launches", C.c_longlong * 4),
-                ("kern_bytes", C.c_double * 4)]
+                ("kern_bytes", C.c_double * 4), ("t_queue_ms", C.c_double),
+                ("batches", C.c_int), ("hbm_bytes", C.c_size_t)]
 
     def as_dict(self):
         return {"t_total_ms": self.t_total_ms, "levels": self.levels,
@@ -49,7 +54,16 @@ class Report(C.Structure):
                 "inner_iters": self.inner_iters, "inner_iters_max": self.inner_iters_max,
                 "restarts": self.restarts, "truncated": self.truncated,
                 "kern_ms": list(self.kern_ms), "kern_launches": list(self.kern_launches),
-                "kern_bytes": list(self.kern_bytes)}
+                "kern_bytes": list(self.kern_bytes), "t_queue_ms": self.t_queue_ms,
+                "batches": self.batches, "hbm_bytes": int(self.hbm_bytes)}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
 
 
 class PlanInfo(C.Structure):
@@ -64,7 +78,7 @@ _I = C.POINTER(C.c_int)
 
 # (name, restype, argtypes) for every entry point of include/dyson.h
 SIGNATURES = [
-    ("dyson_create", C.c_int, [C.POINTER(_P), C.c_int]),
+    ("dyson_create", C.c_int, [C.POINTER(_P), C.c_int, C.c_size_t, C.POINTER(Allocator)]),
     ("dyson_destroy", C.c_int, [_P]),
     ("dyson_plan_create", C.c_int, [_P, C.POINTER(Lattice), C.POINTER(Opts), C.POINTER(_P)]),
     ("dyson_plan_destroy", C.c_int, [_P]),
@@ -76,6 +90,13 @@ SIGNATURES = [
     ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
     ("dyson_correct_level", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _I, _P]),
+    ("dyson_serve_config", C.c_int, [_P, C.c_int, C.c_int]),
+    ("dyson_submit", C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.c_int, C.POINTER(_P)]),
+    ("dyson_poll", C.c_int, [_P, _I]),
+    ("dyson_wait", C.c_int, [_P, C.c_double]),
+    ("dyson_cancel", C.c_int, [_P]),
+    ("dyson_req_report", C.c_int, [_P, C.POINTER(Report)]),
+    ("dyson_release", C.c_int, [_P]),
     ("dyson_last_error", C.c_char_p, []),
     ("dyson_version", C.c_char_p, []),
 ]
@@ -106,9 +127,10 @@ def _check(status):
 
 
 # thin wrappers with the C names --------------------------------------------
-def dyson_create(device: int = 0):
+def dyson_create(device: int = 0, hbm_budget: int = 0, allocator: Allocator | None = None):
     h = _P()
-    _check(load_library().dyson_create(C.byref(h), device))
+    _check(load_library().dyson_create(C.byref(h), device, hbm_budget,
+                                       C.byref(allocator) if allocator is not None else None))
     return h
 
 
@@ -172,6 +194,42 @@ def dyson_correct_level(plan, level, K, d_ptr, G_ptr, steps_np, stream):
     _check(load_library().dyson_correct_level(plan, level, K, d_ptr, G_ptr, sp, stream))
 
 
+def dyson_serve_config(ctx, slots: int, max_batch_freqs: int):
+    _check(load_library().dyson_serve_config(ctx, slots, max_batch_freqs))
+
+
+def dyson_submit(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem):
+    h = _P()
+    _check(load_library().dyson_submit(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem,
+                                       C.byref(h)))
+    return h
+
+
+def dyson_poll(req) -> bool:
+    d = C.c_int()
+    _check(load_library().dyson_poll(req, C.byref(d)))
+    return bool(d.value)
+
+
+def dyson_wait(req, timeout_s: float = -1.0) -> int:
+    """Returns the request's status code (DYSON_ETIMEOUT if unfinished)."""
+    return load_library().dyson_wait(req, float(timeout_s))
+
+
+def dyson_cancel(req):
+    _check(load_library().dyson_cancel(req))
+
+
+def dyson_req_report(req) -> Report:
+    r = Report()
+    _check(load_library().dyson_req_report(req, C.byref(r)))
+    return r
+
+
+def dyson_release(req):
+    _check(load_library().dyson_release(req))
+
+
 # torch-facing helper ---------------------------------------------------------
 def _stream():
     import torch
@@ -188,7 +246,8 @@ class Plan:
 
     def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
-                 inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0):
+                 inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
+                 ctx: "Context | None" = None):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
@@ -201,7 +260,9 @@ class Plan:
         self.n_sites = 1
         for x in dims:
             self.n_sites *= x
-        self.ctx = dyson_create(device)
+        self._own_ctx = ctx is None
+        self.context = ctx if ctx is not None else Context(device)
+        self.ctx = self.context.handle
         self.plan = dyson_plan_create(self.ctx, lat, o)
         self.info = dyson_plan_get_info(self.plan)
 
@@ -209,9 +270,10 @@ class Plan:
         if getattr(self, "plan", None):
             dyson_plan_destroy(self.plan)
             self.plan = None
-        if getattr(self, "ctx", None):
-            dyson_destroy(self.ctx)
-            self.ctx = None
+        if getattr(self, "_own_ctx", False) and getattr(self, "context", None):
+            self.context.close()
+        self.context = None
+        self.ctx = None
 
     def __del__(self):
         try:
@@ -271,6 +333,31 @@ class Plan:
                       _ptr(u), _stream())
         return u
 
+    def submit(self, V, omega, sigma, G=None, mem=MEM_DEVICE):
+        """Queue a solve on the context's server.  mem=MEM_DEVICE: torch tensors on
+        the GPU (complete when submitted); mem=MEM_HOST: numpy arrays (V float64 [N],
+        omega float64 [K], sigma complex128 [K, N]), G a complex128 [K, N] array."""
+        import numpy as np
+        K = int(omega.shape[0])
+        if mem == MEM_DEVICE:
+            import torch
+            if G is None:
+                G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
+            keep = (self._c(V), self._c(omega), self._c(sigma), self._c(G))
+            h = dyson_submit(self.plan, K, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]),
+                             _ptr(keep[3]), MEM_DEVICE)
+        else:
+            V = np.ascontiguousarray(V, np.float64)
+            omega = np.ascontiguousarray(omega, np.float64)
+            sigma = np.ascontiguousarray(sigma, np.complex128)
+            if G is None:
+                G = np.empty((K, self.n_sites), np.complex128)
+            assert G.dtype == np.complex128 and G.flags.c_contiguous
+            keep = (V, omega, sigma, G)
+            cp = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
+            h = dyson_submit(self.plan, K, cp(V), cp(omega), cp(sigma), cp(G), MEM_HOST)
+        return Request(h, G, keep)
+
     def correct_level(self, level, d, Gacc):
         import numpy as np
         K = int(d.shape[0])
@@ -278,3 +365,72 @@ class Plan:
         dyson_correct_level(self.plan, level, K, _ptr(self._c(d)), _ptr(self._c(Gacc)), steps,
                             _stream())
         return steps.reshape(K, self.info.n_nodes[level])
+
+
+class Context:
+    """A device context; its server runs the requests of every plan made on it."""
+
+    def __init__(self, device=0, hbm_budget=0, slots=None, max_batch_freqs=None,
+                 allocator: Allocator | None = None):
+        import weakref
+        self._alloc = allocator  # the callbacks must outlive the context
+        self._plans = weakref.WeakSet()
+        self.handle = dyson_create(device, hbm_budget, allocator)
+        if slots is not None or max_batch_freqs is not None:
+            dyson_serve_config(self.handle, slots or 3, max_batch_freqs or 256)
+
+    def plan(self, dims, **kw) -> Plan:
+        p = Plan(dims, ctx=self, **kw)
+        self._plans.add(p)
+        return p
+
+    def close(self):
+        """Destroys the context after the plans made on it."""
+        if getattr(self, "handle", None):
+            for p in list(self._plans):
+                p.close()
+            dyson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Request:
+    """Handle of a submitted solve; G is filled when it finishes successfully."""
+
+    def __init__(self, handle, G, keep):
+        self.handle, self.G, self._keep = handle, G, keep
+
+    def done(self) -> bool:
+        return dyson_poll(self.handle)
+
+    def wait(self, timeout=None):
+        """Wait and return G; raises DysonError on failure or timeout."""
+        st = dyson_wait(self.handle, -1.0 if timeout is None else float(timeout))
+        _check(st)
+        return self.G
+
+    def status(self, timeout=None) -> int:
+        return dyson_wait(self.handle, -1.0 if timeout is None else float(timeout))
+
+    def cancel(self):
+        dyson_cancel(self.handle)
+
+    def report(self) -> dict:
+        return dyson_req_report(self.handle).as_dict()
+
+    def release(self):
+        if self.handle is not None:
+            dyson_release(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

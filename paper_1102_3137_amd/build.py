@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdyson_mi355x.so")
-SOURCES = ["plan.cpp", "kernels.hip", "cocg.hip", "solver.cpp"]
+SOURCES = ["plan.cpp", "kernels.hip", "cocg.hip", "solver.cpp", "serve.cpp"]
 ARCH = os.environ.get("DYSON_OFFLOAD_ARCH", "gfx950")
 
 
@@ -22,7 +22,7 @@ def _hipcc():
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP/C++ source into the shared library; returns its path."""
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
            # packed FP32 instructions are kept out of every kernel
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",

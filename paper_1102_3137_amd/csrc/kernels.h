@@ -80,6 +80,10 @@ void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, d
 void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat, hipStream_t s);
 void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const double* omega,
                      const double* sigma, double* d, hipStream_t s);
+// eq. (1) input checks, OR-ed into *flag: 1 non-finite V, 2 w_k <= 0 or
+// non-finite, 4 non-finite Sigma, 8 Im(i w_k - Sigma_i) <= 0.
+void launch_validate(int N, int K, const double* V, const double* omega, const double* sigma,
+                     int* flag, hipStream_t s);
 // Tile block factors of graph g (complex128 / complex64 / complex32 storage).
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s);

@@ -50,6 +50,23 @@ __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restric
   st(d, (size_t)k * NP + p, v);
 }
 
+// Input checks of eq. (1); Im(i w_k - Sigma_i) > 0 keeps Im H positive
+// definite, which the pivot-free factorizations rely on.
+__global__ void k_validate(int N, const double* __restrict__ V, const double* __restrict__ omega,
+                           const double* __restrict__ sigma, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= N) return;
+  int f = 0;
+  const double om = omega[k];
+  if (!isfinite(om) || !(om > 0.0)) f |= 2;
+  if (k == 0 && !isfinite(V[i])) f |= 1;
+  const cd sg = ld(sigma, (size_t)k * N + i);
+  if (!isfinite(sg.x) || !isfinite(sg.y)) f |= 4;
+  else if (!(om - sg.y > 0.0)) f |= 8;
+  if (f) atomicOr(flag, f);
+}
+
 // ------------------------------------------------------ tile factorization
 // Block LDL^T of the tile block restricted to the sites active in graph g,
 // block rows = slices of n sites (a row of a square tile, a plane of a cubic
@@ -524,6 +541,11 @@ void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const
   size_t NP = (size_t)G.T * G.S;
   dim3 grid((unsigned)((NP + 255) / 256), K);
   k_assemble<<<grid, 256, 0, s>>>(G, K, mu, V, omega, sigma, d);
+}
+void launch_validate(int N, int K, const double* V, const double* omega, const double* sigma,
+                     int* flag, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), K);
+  k_validate<<<grid, 256, 0, s>>>(N, V, omega, sigma, flag);
 }
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s) {

@@ -13,8 +13,7 @@
 #include <vector>
 
 #include "../../include/dyson.h"
-#include "kernels.h"
-#include "plan.h"
+#include "engine.h"
 
 using namespace dyson;
 
@@ -52,91 +51,31 @@ dyson_status dalloc(T** p, size_t n) {
   return DYSON_OK;
 }
 
-struct DevLevel {
-  int n = 0;
-  int* tile_node = nullptr;
-  int* tlo = nullptr;
-  int* thi = nullptr;
-  int* mcap = nullptr;
-};
-
-// Event-timed kernel classes (report.kern_*).
-struct Prof {
-  bool on = false;
-  std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-  size_t used = 0;
-  long long launches[4] = {0, 0, 0, 0};
-  double bytes[4] = {0, 0, 0, 0};
-  hipEvent_t get() {
-    if (used == pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      pool.push_back(e);
-    }
-    return pool[used++];
-  }
-  void reset() {
-    used = 0;
-    marks.clear();
-    for (int c = 0; c < 4; ++c) launches[c] = 0, bytes[c] = 0;
-  }
-  ~Prof() {
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-};
-
 }  // namespace
 
-struct dyson_ctx {
-  int device = 0;
-};
+namespace dyson {
 
-struct dyson_plan {
-  dyson_ctx* ctx = nullptr;
-  HostPlan hp;
-  TileGeom geom{};
-  int* d_nbr = nullptr;
-  uint8_t* d_kind = nullptr;
-  uint8_t* d_depth = nullptr;
-  int* d_site_of = nullptr;
-  int* d_pos_of = nullptr;
-  std::vector<DevLevel> lv;
-  int kcap = 1;     // largest Lanczos step cap + 1 (basis vectors)
-  int nmax = 1;     // most domains on one level
-  // workspace for up to Kcap frequencies
-  int Kcap = 0;
-  std::vector<void*> allocs;
-  double *d = nullptr, *gacc = nullptr, *xB = nullptr, *xH = nullptr, *r = nullptr, *z = nullptr,
-         *p0 = nullptr, *p1 = nullptr, *s = nullptr, *rhs = nullptr, *R = nullptr, *Q = nullptr;
-  void* fac[2] = {nullptr, nullptr};
-  double* fac64 = nullptr;  // complex128 leaf factors written with the leaf diagonal
-  int fac_g[2] = {-1000, -1000};
-  double* partial = nullptr;
-  double *hpart = nullptr, *h = nullptr;
-  int hstride = 1;
-  CocgState cst{};
-  int *lz_stopped = nullptr, *lz_steps = nullptr;
-  double* Dl = nullptr;     // diagonal correction of the level being run
-  double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
-         *lz_scal = nullptr;
-  int* d_count = nullptr;
-  double* rho2 = nullptr;   // inner solves: r^T z of the last two iterations per item
-  double* partS = nullptr;  // inner solves: per-unit p^T A p
-  std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
-  int* h_count = nullptr;  // pinned
-  unsigned long long* d_prof = nullptr;
-  unsigned long long* d_wprof = nullptr;  // [4][K*nmax] per-item byte counts (profiling):
-                                          // inner solves in [0,2), Lanczos in [2,4)
-  uint64_t* d_fkey = nullptr;
-  Prof prof;
-  // run statistics of the current call
-  long long stat_inner = 0;
-  int stat_inner_max = 0;
-  int stat_restarts = 0;
-  int stat_capped = 0;      // items stopped by the step cap before exhaustion
-  dyson_status pending = DYSON_OK;
-};
+void set_error(const std::string& msg) { g_err = msg; }
+const std::string& get_error() { return g_err; }
+
+hipEvent_t Prof::get() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+void Prof::reset() {
+  used = 0;
+  marks.clear();
+  for (int c = 0; c < 4; ++c) launches[c] = 0, bytes[c] = 0;
+}
+Prof::~Prof() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace dyson
 
 namespace {
 
@@ -149,100 +88,122 @@ int step_cap(int m, const dyson_opts& o) {
   return c;
 }
 
-void free_workspace(dyson_plan* p) {
-  for (void* a : p->allocs) (void)hipFree(a);
-  p->allocs.clear();
-  if (p->h_count) (void)hipHostFree(p->h_count);
-  p->h_count = nullptr;
-  p->Kcap = 0;
-  p->fac_g[0] = p->fac_g[1] = -1000;
-}
-
-template <typename T>
-dyson_status walloc(dyson_plan* p, T** ptr, size_t n) {
-  CHECKED(dalloc(ptr, n));
-  p->allocs.push_back((void*)*ptr);
-  return DYSON_OK;
-}
-
-dyson_status ensure_workspace(dyson_plan* p, int K) {
-  if (K <= p->Kcap) return DYSON_OK;
-  HIPC(hipSetDevice(p->ctx->device));
-  free_workspace(p);
+// Every device buffer of a Work for K frequencies, with its size in bytes.
+// The one table serves allocation and the footprint query.
+std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, int K) {
   const HostPlan& P = p->hp;
   const size_t NP = (size_t)P.T * P.S;
-  const size_t V = (size_t)K * NP * 2;  // doubles per complex vector
-  CHECKED(walloc(p, &p->d, V));
-  CHECKED(walloc(p, &p->gacc, V));
-  CHECKED(walloc(p, &p->xB, V));
-  CHECKED(walloc(p, &p->xH, V));
-  CHECKED(walloc(p, &p->r, V));
-  CHECKED(walloc(p, &p->z, V));
-  CHECKED(walloc(p, &p->p0, V));
-  CHECKED(walloc(p, &p->p1, V));
-  CHECKED(walloc(p, &p->s, V));
-  CHECKED(walloc(p, &p->rhs, V));
-  CHECKED(walloc(p, &p->R, V));
-  CHECKED(walloc(p, &p->Dl, V));
-  const int nq = P.levels.empty() ? 1 : (p->kcap + 1);
-  CHECKED(walloc(p, &p->Q, V * (size_t)nq));
+  const size_t V = (size_t)K * NP * 16;  // bytes per complex vector
+  const size_t nq = P.levels.empty() ? 1 : (size_t)(p->kcap + 1);
   const size_t fe = (size_t)K * P.T * P.sy * P.sx * P.sx * 2;  // reals per factor set
-  for (int i = 0; i < 2; ++i) {
-    if (P.opts.precision == DYSON_PREC_FP64) {
-      double* f;
-      CHECKED(walloc(p, &f, fe));
-      p->fac[i] = f;
-      if (i == 0) p->fac64 = f;  // the leaf factors are the deepest B preconditioner
-      continue;
-    }
-    if (P.opts.precision == DYSON_PREC_MIXED) {
-      float* f;
-      CHECKED(walloc(p, &f, fe));
-      p->fac[i] = f;
-    } else if (P.opts.precision == DYSON_PREC_MIXED16) {
-      uint16_t* f;
-      CHECKED(walloc(p, &f, fe));
-      p->fac[i] = f;
-    } else {
-      double* f;
-      CHECKED(walloc(p, &f, fe));
-      p->fac[i] = f;
-    }
-  }
-  if (P.opts.precision != DYSON_PREC_FP64) CHECKED(walloc(p, &p->fac64, fe));
-  CHECKED(walloc(p, &p->partial, (size_t)K * P.T * 4));
-  CHECKED(walloc(p, &p->hpart, (size_t)K * P.T * p->hstride * 2));
+  const size_t fsz = (P.opts.precision == DYSON_PREC_MIXED)     ? 4
+                     : (P.opts.precision == DYSON_PREC_MIXED16) ? 2
+                                                                : 8;
   const size_t ni = (size_t)K * p->nmax;
-  CHECKED(walloc(p, &p->h, ni * p->hstride * 2));
-  CHECKED(walloc(p, &p->cst.done, ni));
-  CHECKED(walloc(p, &p->cst.iters, ni));
-  CHECKED(walloc(p, &p->cst.bn2, ni));
-  CHECKED(walloc(p, &p->rho2, ni * 4));
-  CHECKED(walloc(p, &p->partS, (size_t)K * P.T * 2));
-  CHECKED(walloc(p, &p->lz_stopped, ni));
-  CHECKED(walloc(p, &p->lz_steps, ni));
-  CHECKED(walloc(p, &p->lz_alpha, ni * 2));
-  CHECKED(walloc(p, &p->lz_beta, ni * 2));
-  CHECKED(walloc(p, &p->lz_unorm2, ni));
-  CHECKED(walloc(p, &p->lz_umax2, ni));
-  CHECKED(walloc(p, &p->lz_scal, ni * 2));
-  CHECKED(walloc(p, &p->d_count, 4));
-  CHECKED(walloc(p, &p->d_prof, 8));
-  CHECKED(walloc(p, &p->d_wprof, 4 * ni));
-  HIPC(hipMemset(p->d_wprof, 0, 4 * ni * sizeof(unsigned long long)));
-  CHECKED(walloc(p, &p->d_fkey, (size_t)K));
-  HIPC(hipHostMalloc((void**)&p->h_count, 4 * sizeof(int), hipHostMallocDefault));
-  p->Kcap = K;
-  return DYSON_OK;
+  std::vector<std::pair<void**, size_t>> t = {
+      {(void**)&w->d, V},          {(void**)&w->gacc, V},      {(void**)&w->xB, V},
+      {(void**)&w->xH, V},         {(void**)&w->r, V},         {(void**)&w->z, V},
+      {(void**)&w->p0, V},         {(void**)&w->p1, V},        {(void**)&w->s, V},
+      {(void**)&w->rhs, V},        {(void**)&w->R, V},         {(void**)&w->Dl, V},
+      {(void**)&w->Q, V * nq},     {&w->fac[0], fe * fsz},     {&w->fac[1], fe * fsz},
+      {(void**)&w->partial, (size_t)K * P.T * 4 * 8},
+      {(void**)&w->hpart, (size_t)K * P.T * p->hstride * 16},
+      {(void**)&w->h, ni * p->hstride * 16},
+      {(void**)&w->cst.done, ni * 4},  {(void**)&w->cst.iters, ni * 4},
+      {(void**)&w->cst.bn2, ni * 8},   {(void**)&w->rho2, ni * 32},
+      {(void**)&w->partS, (size_t)K * P.T * 16},
+      {(void**)&w->lz_stopped, ni * 4}, {(void**)&w->lz_steps, ni * 4},
+      {(void**)&w->lz_alpha, ni * 16},  {(void**)&w->lz_beta, ni * 16},
+      {(void**)&w->lz_unorm2, ni * 8},  {(void**)&w->lz_umax2, ni * 8},
+      {(void**)&w->lz_scal, ni * 16},   {(void**)&w->d_count, 16},
+      {(void**)&w->d_prof, 64},         {(void**)&w->d_wprof, 4 * ni * 8},
+      {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 8},
+      {(void**)&w->d_flag, 16}};
+  // mixed plans keep complex128 leaf factors beside the low-precision ones;
+  // FP64 plans use the first factor slot for them
+  if (P.opts.precision != DYSON_PREC_FP64) t.push_back({(void**)&w->fac64, fe * 8});
+  return t;
+}
+
+void* dev_alloc(const dyson_ctx* c, size_t n, hipStream_t s) {
+  if (c->has_alloc) return c->alloc.alloc(n, (void*)s, c->alloc.user);
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, n) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return ptr;
+}
+
+void dev_free(const dyson_ctx* c, void* ptr, hipStream_t s) {
+  if (!ptr) return;
+  if (c->has_alloc) c->alloc.free(ptr, (void*)s, c->alloc.user);
+  else (void)hipFree(ptr);
 }
 
 }  // namespace
+
+namespace dyson {
+
+size_t work_bytes(const dyson_plan* p, int K) {
+  Work tmp;
+  size_t b = 0;
+  for (auto& e : work_table(p, &tmp, K)) b += (e.second + 255) / 256 * 256;
+  return b;
+}
+
+void free_work(Work* w, hipStream_t s) {
+  const dyson_ctx* c = w->plan ? w->plan->ctx : nullptr;
+  if (c) {
+    (void)hipSetDevice(c->device);
+    for (void* a : w->allocs) dev_free(c, a, s);
+  }
+  w->allocs.clear();
+  if (w->h_count) (void)hipHostFree(w->h_count);
+  w->h_count = nullptr;
+  w->Kcap = 0;
+  w->bytes = 0;
+  w->plan = nullptr;
+  w->fac_g[0] = w->fac_g[1] = -1000;
+  w->pred.clear();
+}
+
+dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s) {
+  if (w->plan == p && K <= w->Kcap) return DYSON_OK;
+  HIPC(hipSetDevice(p->ctx->device));
+  free_work(w, s);
+  w->plan = p;
+  for (auto& e : work_table(p, w, K)) {
+    void* ptr = dev_alloc(p->ctx, e.second ? e.second : 1, s);
+    if (!ptr) {
+      const size_t want = e.second;
+      free_work(w, s);
+      return fail(DYSON_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    *e.first = ptr;
+    w->allocs.push_back(ptr);
+    w->bytes += (e.second + 255) / 256 * 256;
+  }
+  if (p->hp.opts.precision == DYSON_PREC_FP64) w->fac64 = (double*)w->fac[0];
+  HIPC(hipMemsetAsync(w->d_wprof, 0, 4 * (size_t)K * p->nmax * sizeof(unsigned long long), s));
+  if (hipHostMalloc((void**)&w->h_count, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    w->h_count = nullptr;
+    free_work(w, s);
+    return fail(DYSON_ENOMEM, "pinned host allocation failed");
+  }
+  w->Kcap = K;
+  return DYSON_OK;
+}
+
+}  // namespace dyson
 
 namespace {
 
 // ----------------------------------------------------------- the solver
 struct Run {
   dyson_plan* p;
+  Work* w;
   int K;
   hipStream_t s;
   const HostPlan& P() const { return p->hp; }
@@ -250,7 +211,7 @@ struct Run {
   // Time a launch when profiling: class c, algorithmic bytes b.
   template <typename Fn>
   void timed(int c, Fn fn) {
-    Prof& pr = p->prof;
+    Prof& pr = w->prof;
     // profile = 1: events around the inner-solve update kernel only (the
     // dominant kernel); profile >= 2: around every timed kernel class
     if (!pr.on || (P().opts.profile < 2 && c != 0)) {
@@ -267,29 +228,29 @@ struct Run {
   }
 
   dyson_status count_open(const int* flags, int n, int* out) {
-    launch_count_open(flags, n, p->d_count, s);
-    HIPC(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    launch_count_open(flags, n, w->d_count, s);
+    HIPC(hipMemcpyAsync(w->h_count, w->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    *out = p->h_count[0];
+    *out = w->h_count[0];
     return DYSON_OK;
   }
 
   // Factor the tile blocks of graph g (cached in one of two slots).
   dyson_status factors_for(int g, int level, void** fac) {
     for (int i = 0; i < 2; ++i)
-      if (p->fac_g[i] == g) {
-        *fac = p->fac[i];
+      if (w->fac_g[i] == g) {
+        *fac = w->fac[i];
         return DYSON_OK;
       }
     // evict the slot not holding the other graph of this level
-    int slot = (p->fac_g[0] == g + 1 || p->fac_g[0] == g - 1) ? 1 : 0;
+    int slot = (w->fac_g[0] == g + 1 || w->fac_g[0] == g - 1) ? 1 : 0;
     (void)level;  // every tile is factored: a graph is shared by two levels
-    launch_factor(p->geom, K, g, nullptr, p->d, p->fac[slot],
+    launch_factor(p->geom, K, g, nullptr, w->d, w->fac[slot],
                   P().opts.precision == DYSON_PREC_MIXED, P().opts.precision == DYSON_PREC_MIXED16,
                   s);
     HIPC(hipGetLastError());
-    p->fac_g[slot] = g;
-    *fac = p->fac[slot];
+    w->fac_g[slot] = g;
+    *fac = w->fac[slot];
     return DYSON_OK;
   }
 
@@ -305,56 +266,56 @@ struct Run {
     c.g = g;
     c.tile_node = L.tile_node;
     c.n_nodes = L.n;
-    c.item_skip = p->lz_stopped;
-    c.st = p->cst;
-    c.d = p->d;
+    c.item_skip = w->lz_stopped;
+    c.st = w->cst;
+    c.d = w->d;
     c.x = x;
-    c.r = p->r;
-    c.z = p->z;
-    c.p_old = p->p0;
-    c.p_new = p->p1;
-    c.s = p->s;
+    c.r = w->r;
+    c.z = w->z;
+    c.p_old = w->p0;
+    c.p_new = w->p1;
+    c.s = w->s;
     c.fac = fac;
     c.fp32 = HP.opts.precision == DYSON_PREC_MIXED;
     c.fp16 = HP.opts.precision == DYSON_PREC_MIXED16;
-    c.wctr = p->prof.on ? p->d_wprof : nullptr;
+    c.wctr = w->prof.on ? w->d_wprof : nullptr;
     c.tlo = L.tlo;
     c.thi = L.thi;
     c.n_items = K * L.n;
-    c.partS = p->partS;
-    c.partU = p->partial;
-    c.rho2 = p->rho2;
+    c.partS = w->partS;
+    c.partU = w->partial;
+    c.rho2 = w->rho2;
     c.tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
     const int slot = 2 * level + (g == level ? 0 : 1);
-    if ((int)p->pred.size() <= slot) p->pred.resize(slot + 1, 0);
+    if ((int)w->pred.size() <= slot) w->pred.resize(slot + 1, 0);
     launch_cocg_init(c, b, s);
-    launch_cocg_check(c, 0, p->d_count, s);
+    launch_cocg_check(c, 0, w->d_count, s);
     const int maxit = HP.opts.max_inner_iters;
     int it = 0, open = 1;
-    int check_at = std::max(1, p->pred[slot] - 1);
+    int check_at = std::max(1, w->pred[slot] - 1);
     while (it < maxit) {
       timed(1, [&] { launch_cocg_stencil(c, it, s); });
       timed(0, [&] { launch_cocg_update(c, it, s); });
       std::swap(c.p_old, c.p_new);
       ++it;
       if (it >= check_at || it == maxit) {
-        launch_cocg_check(c, it, p->d_count, s);
-        HIPC(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        launch_cocg_check(c, it, w->d_count, s);
+        HIPC(hipMemcpyAsync(w->h_count, w->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
-        open = p->h_count[0];
+        open = w->h_count[0];
         if (open == 0) break;
         check_at = it + (it < 8 ? 1 : 2);
       }
     }
     HIPC(hipGetLastError());
     if (open != 0) {
-      p->pending = DYSON_ENOCONV;
+      w->pending = DYSON_ENOCONV;
       g_err = "inner COCG solve hit max_inner_iters";
     }
-    if (p->prof.on) launch_prof_collect(p->d_wprof, K * L.n, 2, 0, p->d_prof, s);
-    p->pred[slot] = it;
-    p->stat_inner += it;
-    p->stat_inner_max = std::max(p->stat_inner_max, it);
+    if (w->prof.on) launch_prof_collect(w->d_wprof, K * L.n, 2, 0, w->d_prof, s);
+    w->pred[slot] = it;
+    w->stat_inner += it;
+    w->stat_inner_max = std::max(w->stat_inner_max, it);
     return DYSON_OK;
   }
 
@@ -365,30 +326,30 @@ struct Run {
     a.tile_node = p->lv[level].tile_node;
     a.n_nodes = p->lv[level].n;
     a.seed = P().opts.seed;
-    a.fkey = p->d_fkey;
-    a.stopped = p->lz_stopped;
-    a.steps = p->lz_steps;
-    a.alpha = p->lz_alpha;
-    a.beta = p->lz_beta;
-    a.unorm2 = p->lz_unorm2;
-    a.umax2 = p->lz_umax2;
-    a.scal = p->lz_scal;
-    a.partial = p->partial;
-    a.hpart = p->hpart;
-    a.h = p->h;
+    a.fkey = w->d_fkey;
+    a.stopped = w->lz_stopped;
+    a.steps = w->lz_steps;
+    a.alpha = w->lz_alpha;
+    a.beta = w->lz_beta;
+    a.unorm2 = w->lz_unorm2;
+    a.umax2 = w->lz_umax2;
+    a.scal = w->lz_scal;
+    a.partial = w->partial;
+    a.hpart = w->hpart;
+    a.h = w->h;
     a.hstride = p->hstride;
     a.tlo = p->lv[level].tlo;
     a.thi = p->lv[level].thi;
     a.n_items = K * p->lv[level].n;
-    a.wctr = p->prof.on ? p->d_wprof + 2 * (size_t)K * p->nmax : nullptr;
+    a.wctr = w->prof.on ? w->d_wprof + 2 * (size_t)K * p->nmax : nullptr;
     return a;
   }
 
   dyson_status reset_items(int level) {
     const size_t ni = (size_t)K * p->lv[level].n;
-    HIPC(hipMemsetAsync(p->lz_stopped, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(p->lz_steps, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(p->lz_beta, 0, ni * 2 * sizeof(double), s));
+    HIPC(hipMemsetAsync(w->lz_stopped, 0, ni * sizeof(int), s));
+    HIPC(hipMemsetAsync(w->lz_steps, 0, ni * sizeof(int), s));
+    HIPC(hipMemsetAsync(w->lz_beta, 0, ni * 2 * sizeof(double), s));
     return DYSON_OK;
   }
 
@@ -396,20 +357,20 @@ struct Run {
   dyson_status xmatvec(int level, const double* q, double* u) {
     void *facB = nullptr, *facH = nullptr;
     CHECKED(factors_for(level + 1, level, &facB));
-    CHECKED(cocg(level, level + 1, facB, q, p->xB));        // w = B^{-1} q_B   (11)
+    CHECKED(cocg(level, level + 1, facB, q, w->xB));        // w = B^{-1} q_B   (11)
     LzArgs a = lz_args(level);
-    launch_lz_defect(a, K, q, p->xB, p->rhs, s);             // q - H w
+    launch_lz_defect(a, K, q, w->xB, w->rhs, s);             // q - H w
     CHECKED(factors_for(level, level, &facH));
-    CHECKED(cocg(level, level, facH, p->rhs, u));            // u = v - w        (10),(12)
+    CHECKED(cocg(level, level, facH, w->rhs, u));            // u = v - w        (10),(12)
     return DYSON_OK;
   }
 
   void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
-      timed(3, [&] { launch_cgs_dot(a, K, p->Q, qstride, nvec, p->R, s); });
+      timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, s); });
       launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, s);
-      timed(2, [&] { launch_cgs_update(a, K, p->Q, qstride, nvec, p->R, p->Dl, s); });
+      timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, w->Dl, s); });
     }
   }
 
@@ -421,9 +382,9 @@ struct Run {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
     const size_t V = (size_t)K * HP.T * HP.S * 2;
-    auto Qj = [&](int j) { return p->Q + (size_t)j * V; };
+    auto Qj = [&](int j) { return w->Q + (size_t)j * V; };
     CHECKED(reset_items(level));
-    HIPC(hipMemsetAsync(p->Dl, 0, V * sizeof(double), s));
+    HIPC(hipMemsetAsync(w->Dl, 0, V * sizeof(double), s));
     LzArgs a = lz_args(level);
     const int n_items = K * L.n;
     const double brk = 1e-6;  // |r^T r| <= brk |r|^2 would give |q| >= 1e3: redo the item
@@ -439,26 +400,26 @@ struct Run {
       HIPC(hipGetLastError());
       for (int j = 0; j < kmax; ++j) {
         int open = 0;
-        CHECKED(count_open(p->lz_stopped, n_items, &open));
+        CHECKED(count_open(w->lz_stopped, n_items, &open));
         if (open == 0) break;
         const double* q = Qj(j);
-        CHECKED(xmatvec(level, q, p->xH));
-        launch_lz_alpha(a, K, q, p->xH, s);
+        CHECKED(xmatvec(level, q, w->xH));
+        launch_lz_alpha(a, K, q, w->xH, s);
         launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 1, j, HP.opts.lanczos_tol, brk, s);
-        launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, p->xH, p->R, p->Dl, s);
+        launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, w->xH, w->R, w->Dl, s);
         cgs2(a, L, j + 1);
-        launch_lz_norms(a, K, p->R, s);
+        launch_lz_norms(a, K, w->R, s);
         launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, s);
-        if (j + 1 < p->kcap) launch_lz_next(a, K, p->R, Qj(j + 1), s);
+        if (j + 1 < p->kcap) launch_lz_next(a, K, w->R, Qj(j + 1), s);
         HIPC(hipGetLastError());
       }
-      HIPC(hipMemcpyAsync(stop.data(), p->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPC(hipMemcpyAsync(st.data(), p->lz_steps, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(stop.data(), w->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(st.data(), w->lz_steps, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
       int bad = 0;
       for (int i = 0; i < n_items; ++i) {
         bad += (stop[i] == 3);
-        if (stop[i] == 2) p->stat_capped += 1;
+        if (stop[i] == 2) w->stat_capped += 1;
       }
       if (std::getenv("DYSON_VERBOSE")) {
         int hist[5] = {0, 0, 0, 0, 0};
@@ -468,48 +429,186 @@ struct Run {
       }
       if (bad == 0) break;
       if (attempt == 2) {
-        p->pending = DYSON_EBREAKDOWN;
+        w->pending = DYSON_EBREAKDOWN;
         g_err = "Lanczos breakdown persisted after restarts";
         break;
       }
-      p->stat_restarts += bad;
-      launch_lz_reopen(a, K, p->Dl, s);
+      w->stat_restarts += bad;
+      launch_lz_reopen(a, K, w->Dl, s);
       HIPC(hipGetLastError());
     }
-    if (p->prof.on) launch_prof_collect(a.wctr, n_items, 2, 2, p->d_prof, s);
-    launch_add_into(a, K, p->Dl, p->gacc, s);
+    if (w->prof.on) launch_prof_collect(a.wctr, n_items, 2, 2, w->d_prof, s);
+    launch_add_into(a, K, w->Dl, w->gacc, s);
     HIPC(hipGetLastError());
     if (steps_out) *steps_out = st;
     return DYSON_OK;
   }
 };
 
-dyson_status validate_inputs_host(const dyson_plan* p, int K) {
-  if (!p) return fail(DYSON_EINVAL, "null plan");
+// Clears the per-call statistics and the factor cache of a Work.
+dyson_status begin_call(dyson_plan* p, Work* w, int K, hipStream_t s) {
+  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
   if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  HIPC(hipSetDevice(p->ctx->device));
+  CHECKED(ensure_work(p, w, K, s));
+  w->pending = DYSON_OK;
+  w->stat_inner = 0;
+  w->stat_inner_max = 0;
+  w->stat_restarts = 0;
+  w->stat_capped = 0;
+  w->fac_g[0] = w->fac_g[1] = -1000;  // factors depend on d, which changes per call
+  launch_freq_keys(nullptr, K, w->d_fkey, s);
   return DYSON_OK;
 }
 
 }  // namespace
 
+namespace dyson {
+
+dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int n, hipStream_t s) {
+  const int N = p->hp.N;
+  HIPC(hipMemsetAsync(w->d_flag, 0, sizeof(int), s));
+  for (int j = 0; j < n; ++j) {
+    if (sl[j].K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+    if (!sl[j].V || !sl[j].omega || !sl[j].sigma || !sl[j].G)
+      return fail(DYSON_EINVAL, "null input or output pointer");
+    launch_validate(N, sl[j].K, sl[j].V, sl[j].omega, sl[j].sigma, w->d_flag, s);
+  }
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(w->h_count, w->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  const int f = w->h_count[0];
+  if (f & 1) return fail(DYSON_EINVAL, "V contains a non-finite value");
+  if (f & 2) return fail(DYSON_EINVAL, "omega_k must be finite and > 0");
+  if (f & 4) return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
+  if (f & 8) return fail(DYSON_EINVAL, "Im(i w_k - Sigma_i) must be > 0 (causal self-energy)");
+  return DYSON_OK;
+}
+
+dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream_t s,
+                       dyson_report* rep, const std::function<bool()>& abort) {
+  auto t0 = std::chrono::steady_clock::now();
+  int K = 0;
+  for (int j = 0; j < n; ++j) K += sl[j].K;
+  CHECKED(begin_call(p, w, K, s));
+  const HostPlan& P = p->hp;
+  w->prof.reset();
+  w->prof.on = P.opts.profile != 0;
+  if (w->prof.on) HIPC(hipMemsetAsync(w->d_prof, 0, 8 * sizeof(unsigned long long), s));
+  Run run{p, w, K, s};
+  const size_t NP = (size_t)P.T * P.S;
+  // a1: diagonal of H, each slice into its rows of the batch
+  for (int j = 0, k0 = 0; j < n; k0 += sl[j].K, ++j) {
+    launch_freq_keys(sl[j].omega, sl[j].K, w->d_fkey + k0, s);
+    launch_assemble(p->geom, sl[j].K, P.mu, sl[j].V, sl[j].omega, sl[j].sigma,
+                    w->d + (size_t)k0 * NP * 2, s);
+  }
+  // a3/a4: leaf factorization and diag(B^{-1})
+  const size_t V = (size_t)K * NP * 2;
+  HIPC(hipMemsetAsync(w->gacc, 0, V * sizeof(double), s));
+  // FP64 plans keep the leaf factors (FP64 buffers); mixed plans only take the
+  // diagonal here and factor the preconditioner again in complex64
+  const bool keep = P.opts.precision == DYSON_PREC_FP64;
+  launch_factor_diag(p->geom, K, w->d, w->fac64, w->gacc, s);
+  HIPC(hipGetLastError());
+  if (keep && !P.levels.empty()) {
+    // the leaf factors double as the preconditioner of the deepest B graph
+    w->fac_g[0] = (int)P.levels.size();
+  }
+  // a5-a9: corrections bottom-up
+  int max_rank_used = 0;
+  long long lsteps = 0;
+  const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
+  for (int l = (int)P.levels.size() - 1; l >= 0; --l) {
+    if (abort && abort()) {
+      HIPC(hipStreamSynchronize(s));
+      return fail(DYSON_ECANCELLED, "cancelled");
+    }
+    std::vector<int> steps;
+    auto tl = std::chrono::steady_clock::now();
+    CHECKED(run.lanczos_level(l, &steps));
+    int lmax = 0;
+    for (int v : steps) max_rank_used = std::max(max_rank_used, v), lsteps += v, lmax = std::max(lmax, v);
+    if (verbose) {
+      std::fprintf(stderr, "[dyson] level %d: %d domains x %d freqs, max steps %d, %.1f ms, inner iters so far %lld\n",
+                   l, p->lv[l].n, K, lmax,
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count(),
+                   w->stat_inner);
+      std::fflush(stderr);
+    }
+    if (w->pending != DYSON_OK) break;
+  }
+  // a8: scatter each slice to natural order
+  for (int j = 0, k0 = 0; j < n; k0 += sl[j].K, ++j)
+    launch_from_tile(p->geom, sl[j].K, w->gacc + (size_t)k0 * NP * 2, sl[j].G, s);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->levels = (int)P.levels.size();
+    rep->max_rank_used = max_rank_used;
+    rep->lanczos_steps = lsteps;
+    rep->inner_iters = w->stat_inner;
+    rep->inner_iters_max = w->stat_inner_max;
+    rep->restarts = w->stat_restarts;
+    rep->truncated = w->stat_capped > 0 ? 1 : 0;
+    rep->batches = 1;
+    rep->hbm_bytes = w->bytes;
+    if (w->prof.on) {
+      unsigned long long wb[8];
+      HIPC(hipMemcpy(wb, w->d_prof, sizeof(wb), hipMemcpyDeviceToHost));
+      for (int c = 0; c < 4; ++c) w->prof.bytes[c] = (double)wb[c];
+      for (auto& m : w->prof.marks) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, m.second.first, m.second.second) == hipSuccess)
+          rep->kern_ms[m.first] += ms;
+      }
+      for (int c = 0; c < 4; ++c) {
+        rep->kern_launches[c] = w->prof.launches[c];
+        rep->kern_bytes[c] = w->prof.bytes[c];
+      }
+    }
+    rep->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return w->pending;
+}
+
+}  // namespace dyson
+
 // ================================================================ C ABI
 extern "C" {
 
 const char* dyson_last_error(void) { return g_err.c_str(); }
-const char* dyson_version(void) { return "dyson-mi355x 0.1 (gfx950)"; }
+const char* dyson_version(void) { return "dyson-mi355x 0.2 (gfx950)"; }
 
-dyson_status dyson_create(dyson_ctx** ctx, int device) {
+dyson_status dyson_create(dyson_ctx** ctx, int device, size_t hbm_budget,
+                          const dyson_allocator* allocator) {
   if (!ctx) return fail(DYSON_EINVAL, "null ctx");
   int n = 0;
   HIPC(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(DYSON_EINVAL, "device ordinal out of range");
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return fail(DYSON_EINVAL, "allocator needs both alloc and free");
   HIPC(hipSetDevice(device));
-  *ctx = new dyson_ctx{device};
+  auto c = std::make_unique<dyson_ctx>();
+  c->device = device;
+  if (allocator) {
+    c->has_alloc = true;
+    c->alloc = *allocator;
+  }
+  if (hbm_budget == 0) {
+    size_t fr = 0, tot = 0;
+    HIPC(hipMemGetInfo(&fr, &tot));
+    hbm_budget = fr / 10 * 9;
+  }
+  c->budget = hbm_budget;
+  *ctx = c.release();
   return DYSON_OK;
 }
 
 dyson_status dyson_destroy(dyson_ctx* ctx) {
-  delete ctx;
+  delete ctx;  // stops the server first (serve.cpp)
   return DYSON_OK;
 }
 
@@ -566,9 +665,12 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
 
 dyson_status dyson_plan_destroy(dyson_plan* p) {
   if (!p) return DYSON_OK;
+  if (p->live_requests.load() > 0)
+    return fail(DYSON_EBUSY, "plan has requests that are not yet released");
   if (p->ctx) {
     (void)hipSetDevice(p->ctx->device);
-    free_workspace(p);
+    dyson::serve_forget_plan(p->ctx, p);
+    free_work(&p->main, nullptr);
     for (auto& d : p->lv) {
       (void)hipFree(d.tile_node);
       (void)hipFree(d.tlo);
@@ -618,69 +720,17 @@ dyson_status dyson_plan_get_maps(const dyson_plan* p, int* h_depth, int* h_is_se
 
 dyson_status dyson_footprint(const dyson_plan* p, int K, size_t* bytes) {
   if (!p || !bytes || K < 1) return fail(DYSON_EINVAL, "bad argument");
-  const HostPlan& P = p->hp;
-  const size_t NP = (size_t)P.T * P.S;
-  const size_t V = (size_t)K * NP * 16;
-  const size_t fsz = (P.opts.precision == DYSON_PREC_MIXED)   ? 8
-                     : (P.opts.precision == DYSON_PREC_MIXED16) ? 4
-                                                                : 16;
-  const size_t nq = P.levels.empty() ? 1 : (size_t)(p->kcap + 1);
-  size_t b = V * (12 + nq);
-  b += 2 * (size_t)K * P.T * P.sy * P.sx * P.sx * fsz;
-  if (P.opts.precision != DYSON_PREC_FP64) b += (size_t)K * P.T * P.sy * P.sx * P.sx * 16;
-  b += (size_t)K * P.T * 2 * 16 + (size_t)K * P.T * p->hstride * 16;
-  b += (size_t)K * p->nmax * p->hstride * 16 + (size_t)K * p->nmax * 200;
-  *bytes = b;
-  return DYSON_OK;
-}
-
-static dyson_status begin(dyson_plan* p, int K, hipStream_t s) {
-  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
-  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
-  HIPC(hipSetDevice(p->ctx->device));
-  CHECKED(ensure_workspace(p, K));
-  p->pending = DYSON_OK;
-  p->stat_inner = 0;
-  p->stat_inner_max = 0;
-  p->stat_restarts = 0;
-  p->stat_capped = 0;
-  p->fac_g[0] = p->fac_g[1] = -1000;  // factors depend on d, which changes per call
-  launch_freq_keys(nullptr, K, p->d_fkey, s);
-  return DYSON_OK;
-}
-
-// Checks eq. (1)'s inputs on the device side copy: w_k > 0, finite values,
-// Im(i w_k - Sigma) > 0.  Copies to the host (validation is not in the hot loop).
-static dyson_status validate_device_inputs(dyson_plan* p, int K, const double* d_V,
-                                           const double* d_omega, const double* d_sigma,
-                                           hipStream_t s) {
-  const int N = p->hp.N;
-  std::vector<double> V(N), om(K), sg((size_t)2 * K * N);
-  HIPC(hipMemcpyAsync(V.data(), d_V, N * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPC(hipMemcpyAsync(om.data(), d_omega, K * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPC(hipMemcpyAsync(sg.data(), d_sigma, sg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
-  for (int i = 0; i < N; ++i)
-    if (!std::isfinite(V[i])) return fail(DYSON_EINVAL, "V contains a non-finite value");
-  for (int k = 0; k < K; ++k) {
-    if (!std::isfinite(om[k]) || om[k] <= 0) return fail(DYSON_EINVAL, "omega_k must be > 0");
-    for (int i = 0; i < N; ++i) {
-      const double re = sg[2 * ((size_t)k * N + i)], im = sg[2 * ((size_t)k * N + i) + 1];
-      if (!std::isfinite(re) || !std::isfinite(im))
-        return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
-      if (!(om[k] - im > 0))
-        return fail(DYSON_EINVAL, "Im(i w_k - Sigma_i) must be > 0 (causal self-energy)");
-    }
-  }
+  *bytes = work_bytes(p, K);
   return DYSON_OK;
 }
 
 dyson_status dyson_assemble(dyson_plan* p, int K, const double* d_V, const double* d_omega,
                             const double* d_sigma, double* d_d, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  CHECKED(begin(p, K, s));
-  launch_assemble(p->geom, K, p->hp.mu, d_V, d_omega, d_sigma, p->d, s);
-  launch_from_tile(p->geom, K, p->d, d_d, s);
+  Work* w = p ? &p->main : nullptr;
+  CHECKED(begin_call(p, w, K, s));
+  launch_assemble(p->geom, K, p->hp.mu, d_V, d_omega, d_sigma, w->d, s);
+  launch_from_tile(p->geom, K, w->d, d_d, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
   return DYSON_OK;
@@ -689,12 +739,13 @@ dyson_status dyson_assemble(dyson_plan* p, int K, const double* d_V, const doubl
 dyson_status dyson_leaf_diag(dyson_plan* p, int K, const double* d_d, double* d_Gleaf,
                              void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  CHECKED(begin(p, K, s));
-  launch_to_tile(p->geom, K, d_d, p->d, 1.0, s);
+  Work* w = p ? &p->main : nullptr;
+  CHECKED(begin_call(p, w, K, s));
+  launch_to_tile(p->geom, K, d_d, w->d, 1.0, s);
   const size_t V = (size_t)K * p->hp.T * p->hp.S * 2;
-  HIPC(hipMemsetAsync(p->gacc, 0, V * sizeof(double), s));
-  launch_factor_diag(p->geom, K, p->d, p->fac64, p->gacc, s);
-  launch_from_tile(p->geom, K, p->gacc, d_Gleaf, s);
+  HIPC(hipMemsetAsync(w->gacc, 0, V * sizeof(double), s));
+  launch_factor_diag(p->geom, K, w->d, w->fac64, w->gacc, s);
+  launch_from_tile(p->geom, K, w->gacc, d_Gleaf, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
   return DYSON_OK;
@@ -703,114 +754,51 @@ dyson_status dyson_leaf_diag(dyson_plan* p, int K, const double* d_d, double* d_
 dyson_status dyson_xmatvec(dyson_plan* p, int level, int K, const double* d_d, const double* d_q,
                            double* d_u, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  CHECKED(begin(p, K, s));
+  Work* w = p ? &p->main : nullptr;
+  CHECKED(begin_call(p, w, K, s));
   if (level < 0 || level >= (int)p->hp.levels.size()) return fail(DYSON_EINVAL, "bad level");
-  launch_to_tile(p->geom, K, d_d, p->d, 1.0, s);
+  launch_to_tile(p->geom, K, d_d, w->d, 1.0, s);
   const size_t V = (size_t)K * p->hp.T * p->hp.S * 2;
-  launch_to_tile(p->geom, K, d_q, p->R, 0.0, s);
-  HIPC(hipMemsetAsync(p->xH, 0, V * sizeof(double), s));
-  Run run{p, K, s};
+  launch_to_tile(p->geom, K, d_q, w->R, 0.0, s);
+  HIPC(hipMemsetAsync(w->xH, 0, V * sizeof(double), s));
+  Run run{p, w, K, s};
   CHECKED(run.reset_items(level));
-  CHECKED(run.xmatvec(level, p->R, p->xH));
-  launch_from_tile(p->geom, K, p->xH, d_u, s);
+  CHECKED(run.xmatvec(level, w->R, w->xH));
+  launch_from_tile(p->geom, K, w->xH, d_u, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
-  return p->pending;
+  return w->pending;
 }
 
 dyson_status dyson_correct_level(dyson_plan* p, int level, int K, const double* d_d,
                                  double* d_Gacc, int* h_steps, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  CHECKED(begin(p, K, s));
+  Work* w = p ? &p->main : nullptr;
+  CHECKED(begin_call(p, w, K, s));
   if (level < 0 || level >= (int)p->hp.levels.size()) return fail(DYSON_EINVAL, "bad level");
-  launch_to_tile(p->geom, K, d_d, p->d, 1.0, s);
-  launch_to_tile(p->geom, K, d_Gacc, p->gacc, 0.0, s);
-  Run run{p, K, s};
+  launch_to_tile(p->geom, K, d_d, w->d, 1.0, s);
+  launch_to_tile(p->geom, K, d_Gacc, w->gacc, 0.0, s);
+  Run run{p, w, K, s};
   std::vector<int> steps;
   CHECKED(run.lanczos_level(level, &steps));
-  launch_from_tile(p->geom, K, p->gacc, d_Gacc, s);
+  launch_from_tile(p->geom, K, w->gacc, d_Gacc, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
   if (h_steps) std::memcpy(h_steps, steps.data(), steps.size() * sizeof(int));
-  return p->pending;
+  return w->pending;
 }
 
 dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* d_omega,
                          const double* d_sigma, double* d_G, void* stream, dyson_report* rep) {
-  auto t0 = std::chrono::steady_clock::now();
+  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
+  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
   hipStream_t s = (hipStream_t)stream;
-  CHECKED(begin(p, K, s));
-  CHECKED(validate_device_inputs(p, K, d_V, d_omega, d_sigma, s));
-  const HostPlan& P = p->hp;
-  p->prof.reset();
-  p->prof.on = P.opts.profile != 0;
-  if (p->prof.on) HIPC(hipMemsetAsync(p->d_prof, 0, 8 * sizeof(unsigned long long), s));
-  Run run{p, K, s};
-  launch_freq_keys(d_omega, K, p->d_fkey, s);
-  // a1: diagonal of H
-  launch_assemble(p->geom, K, P.mu, d_V, d_omega, d_sigma, p->d, s);
-  // a3/a4: leaf factorization and diag(B^{-1})
-  const size_t V = (size_t)K * P.T * P.S * 2;
-  HIPC(hipMemsetAsync(p->gacc, 0, V * sizeof(double), s));
-  // FP64 plans keep the leaf factors (FP64 buffers); mixed plans only take the
-  // diagonal here and factor the preconditioner again in complex64
-  const bool keep = P.opts.precision == DYSON_PREC_FP64;
-  launch_factor_diag(p->geom, K, p->d, p->fac64, p->gacc, s);
-  HIPC(hipGetLastError());
-  if (keep && !P.levels.empty()) {
-    // the leaf factors double as the preconditioner of the deepest B graph
-    p->fac_g[0] = (int)P.levels.size();
-  }
-  // a5-a9: corrections bottom-up
-  int max_rank_used = 0;
-  long long lsteps = 0;
-  const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
-  for (int l = (int)P.levels.size() - 1; l >= 0; --l) {
-    std::vector<int> steps;
-    auto tl = std::chrono::steady_clock::now();
-    CHECKED(run.lanczos_level(l, &steps));
-    int lmax = 0;
-    for (int v : steps) max_rank_used = std::max(max_rank_used, v), lsteps += v, lmax = std::max(lmax, v);
-    if (verbose) {
-      std::fprintf(stderr, "[dyson] level %d: %d domains x %d freqs, max steps %d, %.1f ms, inner iters so far %lld\n",
-                   l, p->lv[l].n, K, lmax,
-                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count(),
-                   p->stat_inner);
-      std::fflush(stderr);
-    }
-    if (p->pending != DYSON_OK) break;
-  }
-  // a8: scatter to natural order
-  launch_from_tile(p->geom, K, p->gacc, d_G, s);
-  HIPC(hipGetLastError());
-  HIPC(hipStreamSynchronize(s));
-  if (rep) {
-    std::memset(rep, 0, sizeof(*rep));
-    rep->levels = (int)P.levels.size();
-    rep->max_rank_used = max_rank_used;
-    rep->lanczos_steps = lsteps;
-    rep->inner_iters = p->stat_inner;
-    rep->inner_iters_max = p->stat_inner_max;
-    rep->restarts = p->stat_restarts;
-    rep->truncated = p->stat_capped > 0 ? 1 : 0;
-    if (p->prof.on) {
-      unsigned long long wb[8];
-      HIPC(hipMemcpy(wb, p->d_prof, sizeof(wb), hipMemcpyDeviceToHost));
-      for (int c = 0; c < 4; ++c) p->prof.bytes[c] = (double)wb[c];
-      for (auto& m : p->prof.marks) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, m.second.first, m.second.second) == hipSuccess)
-          rep->kern_ms[m.first] += ms;
-      }
-      for (int c = 0; c < 4; ++c) {
-        rep->kern_launches[c] = p->prof.launches[c];
-        rep->kern_bytes[c] = p->prof.bytes[c];
-      }
-    }
-    rep->t_total_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  return p->pending;
+  Work* w = &p->main;
+  HIPC(hipSetDevice(p->ctx->device));
+  CHECKED(ensure_work(p, w, K, s));
+  Slice sl{K, d_V, d_omega, d_sigma, d_G};
+  CHECKED(validate_slices(p, w, &sl, 1, s));
+  return run_solve(p, w, &sl, 1, s, rep, nullptr);
 }
 
 }  // extern "C"

@@ -117,3 +117,33 @@ def rect(dims, K: int = 2, seed: int = 7, vc: float = 0.01, mu: float = 0.5,
     fi = tuple(range(K)) if freq_index is None else tuple(freq_index)
     return Workload(dims=tuple(dims), t=-1.0, mu=mu, vc=vc, beta=beta,
                     freq_index=fi, seed=seed, name=f"lattice {dims}, K={len(fi)}")
+
+
+def cubic(L: int, K: int, seed: int = 3, beta: float = 10.0, mu: float = 1.0) -> Workload:
+    """A simple cubic lattice with the 48^3 trap rescaled to keep the edge
+    potential: vc = 1e-3 * (48/L)^2."""
+    return Workload(dims=(L, L, L), t=-1.0, mu=mu, vc=1e-3 * (48.0 / L) ** 2, beta=beta,
+                    freq_index=tuple(range(K)), seed=seed, name=f"cubic {L}^3, K={K}")
+
+
+def serving_trace(n: int, rate: float, squares=(128, 256, 512), cubes=(32, 64),
+                  k_range=(16, 256), beta_range=(5.0, 40.0), seed: int = 5):
+    """A seeded stream of solve requests as a self-consistency loop would emit
+    them: Poisson arrivals at `rate` per second, the lattice drawn uniformly
+    from the squares and cubes, K ~ U{k_range}, beta ~ U[beta_range], and a
+    fresh self-energy per request (seed 1000 + request id).  Returns a list of
+    (arrival time in s, Workload)."""
+    rng = np.random.default_rng(seed)
+    shapes = [("sq", L) for L in squares] + [("cu", L) for L in cubes]
+    t, out = 0.0, []
+    for rid in range(n):
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+        kind, L = shapes[int(rng.integers(len(shapes)))]
+        K = int(rng.integers(k_range[0], k_range[1] + 1))
+        beta = float(rng.uniform(*beta_range))
+        if kind == "sq":
+            w = scaled_square(L, K, seed=1000 + rid, beta=beta)
+        else:
+            w = cubic(L, K, seed=1000 + rid, beta=beta)
+        out.append((t, w))
+    return out

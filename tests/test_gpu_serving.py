@@ -1,0 +1,192 @@
+"""GPU tests of the request server (dyson_submit / poll / wait / cancel /
+release) through the C ABI.
+
+Every (domain, frequency) item is computed the same way whatever batch it
+lands in (its Lanczos start vector is keyed by the bits of w_k, convergence is
+decided per item), so a request's result in a mix of concurrent requests must
+equal, bit for bit, the result of the same request solved alone; the served
+results are also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import device_inputs, oracle_G, have_gpu
+
+pytestmark = pytest.mark.gpu
+
+if have_gpu():
+    import torch
+    from paper_1102_3137_amd import (Context, DysonError, PART_NESTED, PART_SINGLE, PREC_FP64,
+                                     PREC_MIXED16, MEM_HOST, MEM_DEVICE, Allocator)
+    from paper_1102_3137_amd import binding as B
+
+
+def _w(dims, K, seed, beta=10.0):
+    vc = 0.01 * (32.0 / max(dims)) ** 2
+    return synth.rect(dims, K=K, seed=seed, vc=vc, beta=beta)
+
+
+def _plan(ctx, w, s=8, part=0, prec=0):   # nested partition, FP64
+    return ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec)
+
+
+def test_alone_equals_mix_bitwise():
+    ctx = Context(0, slots=3)
+    cases = [  # (workload, leaf edge, partition, precision)
+        (_w((32, 32), 3, 11), 16, PART_SINGLE, PREC_FP64),
+        (_w((48, 40), 5, 12), 8, PART_NESTED, PREC_FP64),
+        (_w((64, 64), 4, 13, beta=20.0), 16, PART_NESTED, PREC_MIXED16),
+        (_w((64, 64), 6, 14, beta=20.0), 16, PART_NESTED, PREC_MIXED16),  # same plan as above
+        (_w((12, 12, 12), 2, 15), 4, PART_NESTED, PREC_FP64),
+    ]
+    plans, inputs, alone = {}, [], []
+    for w, s, part, prec in cases:
+        key = (w.dims, s, part, prec)
+        if key not in plans:
+            plans[key] = _plan(ctx, w, s, part, prec)
+        p = plans[key]
+        V, om, sig, tV, tom, tsig = device_inputs(w)
+        inputs.append((p, w, V, om, sig, tV, tom, tsig))
+        alone.append(p.solve(tV, tom, tsig).cpu().numpy())
+    torch.cuda.synchronize()
+    reqs = [p.submit(tV, tom, tsig) for (p, w, V, om, sig, tV, tom, tsig) in inputs]
+    for i, r in enumerate(reqs):
+        G = r.wait(timeout=120).cpu().numpy()
+        rep = r.report()
+        assert rep["batches"] >= 1 and rep["t_total_ms"] >= rep["t_queue_ms"] >= 0
+        assert np.array_equal(G, alone[i]), f"case {i}: served result differs from alone"
+        r.release()
+    # the FP64 cases: accuracy against the oracle
+    for i in (0, 1, 4):
+        p, w, V, om, sig = inputs[i][:5]
+        ref = oracle_G(w, V, om, sig)
+        assert oracle.rel_err(alone[i], ref) < 1e-10
+    for p in plans.values():
+        p.close()
+    ctx.close()
+
+
+def test_host_mode_matches_device_mode():
+    ctx = Context(0, slots=2)
+    w = _w((40, 36), 3, 21)
+    p = _plan(ctx, w, 8)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    Gd = p.submit(tV, tom, tsig).wait(timeout=120).cpu().numpy()
+    rh = p.submit(V, om, sig, mem=MEM_HOST)
+    Gh = rh.wait(timeout=120)
+    assert isinstance(Gh, np.ndarray)
+    assert np.array_equal(Gd, Gh)
+    assert oracle.rel_err(Gh, oracle_G(w, V, om, sig)) < 1e-10
+    rh.release()
+    p.close()
+    ctx.close()
+
+
+def test_budget_splits_request_into_batches():
+    w = _w((48, 48), 7, 31)
+    probe = Context(0)
+    p0 = _plan(probe, w, 8)
+    need3 = p0.footprint(3)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    ref = p0.solve(tV, tom, tsig).cpu().numpy()
+    p0.close()
+    probe.close()
+    # a budget that holds three frequencies at a time
+    ctx = Context(0, hbm_budget=need3 + 4096, slots=2)
+    p = _plan(ctx, w, 8)
+    r = p.submit(tV, tom, tsig)
+    G = r.wait(timeout=120).cpu().numpy()
+    assert r.report()["batches"] >= 3
+    assert np.array_equal(G, ref)
+    r.release()
+    # a budget below one frequency: the request fails with ENOMEM
+    p.close()
+    ctx.close()
+    tiny = Context(0, hbm_budget=1 << 20)
+    pt = _plan(tiny, w, 8)
+    rt = pt.submit(tV, tom, tsig)
+    assert rt.status(timeout=60) == B.ENOMEM
+    rt.release()
+    pt.close()
+    tiny.close()
+
+
+def test_cancel_timeout_and_busy_plan():
+    ctx = Context(0, slots=1)
+    wa = _w((96, 96), 8, 41, beta=20.0)
+    wb = _w((40, 40), 2, 42)
+    pa, pb = _plan(ctx, wa, 16), _plan(ctx, wb, 8)
+    _, _, _, tVa, toma, tsiga = device_inputs(wa)
+    _, _, _, tVb, tomb, tsigb = device_inputs(wb)
+    Gb = torch.full((wb.n_freq, wb.n_sites), 7.0 + 0j, dtype=torch.complex128, device="cuda:0")
+    ra = pa.submit(tVa, toma, tsiga)
+    rb = pb.submit(tVb, tomb, tsigb, G=Gb)   # queued behind ra on the single slot
+    assert rb.status(timeout=0.0) == B.ETIMEOUT
+    with pytest.raises(DysonError) as e:
+        pb.close()                          # plan with a live request
+    assert e.value.status == B.EBUSY
+    rb.cancel()
+    assert rb.status(timeout=10) == B.ECANCELLED
+    assert torch.all(Gb == 7.0).item()      # never scheduled: G untouched
+    ra.wait(timeout=300)
+    assert ra.done()
+    ra.release()
+    rb.release()
+    pb.close()
+    pa.close()
+    ctx.close()
+
+
+def test_submit_rejects_invalid_inputs():
+    ctx = Context(0)
+    w = _w((24, 24), 2, 51)
+    p = _plan(ctx, w, 8)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    bad = sig.copy()
+    bad[1, 5] = complex(0.0, om[1] + 1.0)          # Im(i w - Sigma) < 0
+    with pytest.raises(DysonError) as e:
+        p.submit(V, om, bad, mem=MEM_HOST)
+    assert e.value.status == B.EINVAL
+    tom_bad = tom.clone()
+    tom_bad[0] = -1.0
+    with pytest.raises(DysonError) as e:
+        p.submit(tV, tom_bad, tsig)
+    assert e.value.status == B.EINVAL
+    Vn = V.copy()
+    Vn[3] = np.nan
+    with pytest.raises(DysonError) as e:
+        p.submit(torch.from_numpy(Vn).cuda(), tom, tsig)
+    assert e.value.status == B.EINVAL
+    p.close()
+    ctx.close()
+
+
+def test_torch_allocator_hook():
+    calls = {"alloc": 0, "free": 0}
+
+    @B.ALLOC_FN
+    def _alloc(n, stream, user):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(int(n), 0, stream)
+
+    @B.FREE_FN
+    def _free(ptr, stream, user):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    al = Allocator(_alloc, _free, None)
+    ctx = Context(0, allocator=al, slots=2)
+    w = _w((32, 40), 2, 61)
+    p = _plan(ctx, w, 8)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    G1 = p.solve(tV, tom, tsig).cpu().numpy()
+    r = p.submit(tV, tom, tsig)
+    G2 = r.wait(timeout=120).cpu().numpy()
+    r.release()
+    assert np.array_equal(G1, G2)
+    assert oracle.rel_err(G1, oracle_G(w, V, om, sig)) < 1e-10
+    p.close()
+    ctx.close()
+    assert calls["alloc"] > 0 and calls["free"] == calls["alloc"]

@@ -118,3 +118,21 @@ def test_planner_rejects_invalid(dims, s):
     with pytest.raises(B.DysonError) as e:
         _host_plan(dims, s, B.PART_NESTED)
     assert e.value.status == 1
+
+
+def test_serving_entry_points_reject_null_handles():
+    """Argument checks of the request API that run before any device call."""
+    lib = B.load_library()
+    h = B._P()
+    assert lib.dyson_submit(None, 1, None, None, None, None, 0, B.C.byref(h)) == B.EINVAL
+    assert lib.dyson_poll(None, None) == B.EINVAL
+    assert lib.dyson_wait(None, 0.0) == B.EINVAL
+    assert lib.dyson_cancel(None) == B.EINVAL
+    assert lib.dyson_req_report(None, None) == B.EINVAL
+    assert lib.dyson_serve_config(None, 1, 1) == B.EINVAL
+    assert lib.dyson_release(None) == B.OK
+    plan = _host_plan((16, 16), 8, B.PART_NESTED)
+    # a plan without a device context cannot take requests
+    assert lib.dyson_submit(plan, 1, None, None, None, None, 0, B.C.byref(h)) == B.EINVAL
+    assert b"device context" in lib.dyson_last_error()
+    B.dyson_plan_destroy(plan)
