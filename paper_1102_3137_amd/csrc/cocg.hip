@@ -7,9 +7,11 @@
 // high-side separator fringe), factored by k_factor as a block LDL^T over
 // the tile's rows of sx sites.
 //
-// Work unit = one (tile, frequency) handled by ONE wavefront; four units
-// per workgroup.  Nothing synchronises across waves: the tile solve passes
-// its row vectors through the wave's own LDS slice.  No data crosses
+// Work unit = one (tile, frequency).  Slices of at most 16 sites (rows of
+// square tiles, planes of 4^3 cubic tiles): ONE wavefront per unit, four
+// units per workgroup, and nothing synchronises across waves: the tile solve
+// passes its row vectors through the wave's own LDS slice.  Plane slices of
+// 25 or 36 sites (cubic tiles of edge 5, 6): one workgroup per unit.  No data crosses
 // workgroups inside a launch (the eight XCDs keep separate L2 caches): each
 // unit writes its partial sums, and the NEXT launch's waves re-reduce the
 // partials of their item in a fixed order (so every wave derives the same
@@ -210,47 +212,11 @@ __device__ __forceinline__ void wave_tile_solve(const WaveFactor<F, REG>& f, con
   }
 }
 
-// Slices wider than 16 sites (planes of cubic tiles): lane i < n owns row i
-// of every S_y^{-1}, read from memory in both sweeps.
-template <typename F>
-__device__ __forceinline__ void wave_tile_solve_rows(const F* fac, size_t fbase, cd* zl,
-                                                     const uint8_t* act, int n, int ns, double tt,
-                                                     int lane) {
-  const size_t nn = (size_t)n * n;
-  wave_sync();
-  for (int y = 1; y < ns; ++y) {
-    if (lane < n) {
-      const size_t row = fbase + (size_t)(y - 1) * nn + (size_t)lane * n;
-      cd acc = cmk(0.0, 0.0);
-      for (int j = 0; j < n; ++j) acc = cfma(ldf<F>(fac, row + j), zl[j + n * (y - 1)], acc);
-      const int l = lane + n * y;
-      if (act[l] && act[l - n]) zl[l] = csub(zl[l], cscale(acc, tt));
-    }
-    wave_sync();
-  }
-  for (int y = ns - 1; y >= 0; --y) {
-    cd acc = cmk(0.0, 0.0);
-    if (lane < n) {
-      const size_t row = fbase + (size_t)y * nn + (size_t)lane * n;
-      for (int j = 0; j < n; ++j) {
-        const int l = j + n * y;
-        cd r = zl[l];
-        if (y < ns - 1 && act[l] && act[l + n]) r = csub(r, cscale(zl[l + n], tt));
-        acc = cfma(ldf<F>(fac, row + j), r, acc);
-      }
-    }
-    wave_sync();
-    if (lane < n) zl[lane + n * y] = acc;
-    wave_sync();
-  }
-}
-
 template <typename F, bool REG>
 __device__ __forceinline__ void tile_solve_any(const WaveFactor<F, REG>& f, const F* fac,
                                                size_t fbase, cd* zl, const uint8_t* act,
                                                const TileGeom& G, int lane) {
-  if (G.sx > 16) wave_tile_solve_rows<F>(fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
-  else wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
+  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
 }
 
 // ------------------------------------------------------------- kernels
@@ -468,6 +434,303 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   cocg_update_body<F, REG>(a, it);
 }
 
+// ------------------------------------------- plane slices: a workgroup per unit
+// Cubic tiles of edge 5 or 6 have slices of n = 25 or 36 sites (planes).  One
+// workgroup (256 threads) handles one (tile, frequency) unit: one thread per
+// site for the vector work, and for the slice sweeps thread (i = tid>>2,
+// c = tid&3) owns columns c*PW .. c*PW+PW-1 of row i of every S_y^{-1}.
+// complex32 / complex64 factors are loaded into registers in one burst at
+// the start, so the 2*ns-1 dependent slice steps wait only on LDS and
+// workgroup barriers; FP64 factors are read per step.
+constexpr int PW = 9;   // columns per thread: 4*PW >= 36
+constexpr int PNS = 6;  // most slices per tile
+
+template <typename F>
+struct PlaneFactor;
+
+template <>
+struct PlaneFactor<__half> {
+  uint32_t g[PNS][PW];
+  __device__ __forceinline__ void load(const __half* fac, size_t fbase, int n, int ns, int i,
+                                       int c) {
+    const uint32_t* f1 = reinterpret_cast<const uint32_t*>(fac) + fbase;
+#pragma unroll
+    for (int y = 0; y < PNS; ++y)
+#pragma unroll
+      for (int e = 0; e < PW; ++e) {
+        const int j = c * PW + e;
+        g[y][e] = (y < ns && i < n && j < n) ? f1[(size_t)y * n * n + i * n + j] : 0u;
+      }
+  }
+  __device__ __forceinline__ cd get(int y, int e, const __half*, size_t, int, int, int) const {
+    uint32_t a = g[y][e];
+    asm volatile("" : "+v"(a));
+    const __half2 h = *reinterpret_cast<const __half2*>(&a);
+    return cmk((double)__low2float(h), (double)__high2float(h));
+  }
+};
+
+template <>
+struct PlaneFactor<float> {
+  uint32_t gr[PNS][PW], gi[PNS][PW];
+  __device__ __forceinline__ void load(const float* fac, size_t fbase, int n, int ns, int i,
+                                       int c) {
+    const float2* f2 = reinterpret_cast<const float2*>(fac) + fbase;
+#pragma unroll
+    for (int y = 0; y < PNS; ++y)
+#pragma unroll
+      for (int e = 0; e < PW; ++e) {
+        const int j = c * PW + e;
+        const float2 v =
+            (y < ns && i < n && j < n) ? f2[(size_t)y * n * n + i * n + j] : make_float2(0.f, 0.f);
+        gr[y][e] = __float_as_uint(v.x);
+        gi[y][e] = __float_as_uint(v.y);
+      }
+  }
+  __device__ __forceinline__ cd get(int y, int e, const float*, size_t, int, int, int) const {
+    uint32_t a = gr[y][e], b = gi[y][e];
+    asm volatile("" : "+v"(a), "+v"(b));
+    return cmk((double)__uint_as_float(a), (double)__uint_as_float(b));
+  }
+};
+
+template <>
+struct PlaneFactor<double> {
+  __device__ __forceinline__ void load(const double*, size_t, int, int, int, int) {}
+  __device__ __forceinline__ cd get(int y, int e, const double* fac, size_t fbase, int n, int i,
+                                    int c) const {
+    const int j = c * PW + e;
+    return (i < n && j < n) ? ld(fac, fbase + (size_t)y * n * n + i * n + j) : cmk(0.0, 0.0);
+  }
+};
+
+// In place over the workgroup: zl = r on entry, z = M^{-1} r on exit; the
+// same block forward / backward sweeps as wave_tile_solve.
+template <typename F>
+__device__ __forceinline__ void plane_tile_solve(const PlaneFactor<F>& f, const F* fac,
+                                                 size_t fbase, cd* zl, const uint8_t* act, int n,
+                                                 int ns, double tt) {
+  const int i = threadIdx.x >> 2, c = threadIdx.x & 3;
+  __syncthreads();
+#pragma unroll
+  for (int y = 1; y < PNS; ++y) {
+    if (y < ns) {
+      cd acc = cmk(0.0, 0.0);
+#pragma unroll
+      for (int e = 0; e < PW; ++e) {
+        const int j = c * PW + e;
+        if (j < n) acc = cfma(f.get(y - 1, e, fac, fbase, n, i, c), zl[j + n * (y - 1)], acc);
+      }
+      acc = quad_sum(acc);
+      if (c == 0 && i < n) {
+        const int l = i + n * y;
+        if (act[l] && act[l - n]) zl[l] = csub(zl[l], cscale(acc, tt));
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int y = PNS - 1; y >= 0; --y) {
+    if (y < ns) {
+      cd acc = cmk(0.0, 0.0);
+#pragma unroll
+      for (int e = 0; e < PW; ++e) {
+        const int j = c * PW + e;
+        if (j < n) {
+          const int l = j + n * y;
+          cd row = zl[l];
+          if (y < ns - 1 && act[l] && act[l + n]) row = csub(row, cscale(zl[l + n], tt));
+          acc = cfma(f.get(y, e, fac, fbase, n, i, c), row, acc);
+        }
+      }
+      acc = quad_sum(acc);
+      __syncthreads();
+      if (c == 0 && i < n) zl[i + n * y] = acc;
+      __syncthreads();
+    }
+  }
+}
+
+// Unit of a workgroup-per-unit launch (uniform over the workgroup).
+__device__ __forceinline__ Unit decode_wg(const CocgLaunch& a) {
+  Unit u;
+  u.wave = threadIdx.x >> 6;
+  u.lane = threadIdx.x & 63;
+  const int id = blockIdx.x;
+  u.ok = id < a.K * a.G.T;
+  u.k = u.ok ? id / a.G.T : 0;
+  u.t = u.ok ? id % a.G.T : 0;
+  u.node = u.ok ? a.tile_node[u.t] : -1;
+  u.item = u.k * a.n_nodes + u.node;
+  u.ok = u.ok && u.node >= 0;
+  return u;
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_cocg_init_planes(CocgLaunch a,
+                                                          const double* __restrict__ b) {
+  const Unit u = decode_wg(a);
+  if (!u.ok) return;
+  if (a.item_skip && a.item_skip[u.item]) return;
+  const TileGeom& G = a.G;
+  __shared__ cd zl[256];
+  __shared__ uint8_t act[256];
+  const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  PlaneFactor<F> f;
+  f.load(fac, fbase, G.sx, G.sy, threadIdx.x >> 2, threadIdx.x & 3);
+  const int l = threadIdx.x;
+  cd rv = cmk(0.0, 0.0);
+  uint8_t ac = 0;
+  if (l < G.S) {
+    const size_t p = (size_t)u.t * G.S + l;
+    ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
+    if (ac) rv = ld(b, base + l);
+  }
+  act[l] = ac;
+  zl[l] = rv;
+  plane_tile_solve<F>(f, fac, fbase, zl, act, G.sx, G.sy, G.t);
+  cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
+  if (l < G.S) {
+    const cd zv = ac ? zl[l] : cmk(0.0, 0.0);
+    st(a.r, base + l, rv);
+    st(a.z, base + l, zv);
+    st(a.x, base + l, cmk(0.0, 0.0));
+    st(a.p_old, base + l, cmk(0.0, 0.0));
+    rz = cmul(rv, zv);
+    rr.x = cabs2(rv);
+  }
+  block_sum2(rz, rr);
+  if (threadIdx.x == 0) {
+    const size_t q = ((size_t)u.k * G.T + u.t) * 2;
+    st(a.partU, q, rz);
+    st(a.partU, q + 1, rr);
+  }
+}
+
+// The stencil launch of k_cocg_stencil, one thread per site.  Values of a
+// neighbouring tile are read together with its activity flags and masked
+// afterwards, so the loads do not wait on the flags.
+__global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
+  const Unit u = decode_wg(a);
+  if (!u.ok || a.st.done[u.item]) return;
+  const TileGeom& G = a.G;
+  const size_t NP = (size_t)G.T * G.S;
+  const size_t kb = (size_t)u.k * NP;
+  const size_t base = kb + (size_t)u.t * G.S;
+  const bool lead = u.t == a.tlo[u.node];
+  cd beta = cmk(0.0, 0.0);
+  if (it > 0) {
+    cd rho, rr;
+    item_sum(a.partU, 2, a, u, rho, rr);
+    if (rr.x <= a.tol2 * a.st.bn2[u.item]) {
+      if (lead && threadIdx.x == 0) {
+        a.st.done[u.item] = 1;
+        a.st.iters[u.item] = it;
+      }
+      return;
+    }
+    beta = cdiv(rho, ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item));
+    if (lead && threadIdx.x == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
+  }
+  if (a.wctr && lead && threadIdx.x == 0)
+    a.wctr[(size_t)1 * a.n_items + u.item] +=
+        (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+        ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
+  __shared__ cd pl[256];
+  const int l = threadIdx.x;
+  bool ac = false;
+  cd pn = cmk(0.0, 0.0);
+  if (l < G.S) {
+    const size_t p = (size_t)u.t * G.S + l;
+    ac = active(G.kind[p], G.depth[p], a.g);
+    if (ac) pn = cfma(beta, ld(a.p_old, base + l), ld(a.z, base + l));
+    st(a.p_new, base + l, pn);
+  }
+  pl[l] = pn;
+  __syncthreads();
+  cd mu = cmk(0.0, 0.0);
+  if (l < G.S) {
+    if (!ac) {
+      st(a.s, base + l, cmk(0.0, 0.0));
+    } else {
+      cd nb = cmk(0.0, 0.0);
+      for (int dir = 0; dir < 2 * G.dim; ++dir) {
+        int nt, nl;
+        if (!site_nbr(G, u.t, l, dir, nt, nl)) continue;
+        if (nt == u.t) {
+          nb = cadd(nb, pl[nl]);
+        } else {
+          const size_t np = (size_t)nt * G.S + nl;
+          const cd po = ld(a.p_old, kb + np), zo = ld(a.z, kb + np);
+          if (active(G.kind[np], G.depth[np], a.g)) nb = cadd(nb, cfma(beta, po, zo));
+        }
+      }
+      const cd sv = cfma(ld(a.d, base + l), pn, cscale(nb, G.t));
+      st(a.s, base + l, sv);
+      mu = cmul(pn, sv);
+    }
+  }
+  cd unused = cmk(0.0, 0.0);
+  block_sum2(mu, unused);
+  if (threadIdx.x == 0) st(a.partS, (size_t)u.k * G.T + u.t, mu);
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it) {
+  const Unit u = decode_wg(a);
+  if (!u.ok || a.st.done[u.item]) return;
+  const TileGeom& G = a.G;
+  const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  cd mu, unused;
+  item_sum(a.partS, 1, a, u, mu, unused);
+  if (cabs2(mu) == 0.0) {
+    if (u.t == a.tlo[u.node] && threadIdx.x == 0) a.st.done[u.item] = 2;
+    return;
+  }
+  const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
+  if (a.wctr && u.t == a.tlo[u.node] && threadIdx.x == 0)
+    a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+                      ((unsigned long long)(G.S * (7 * 16 + 2)) +
+                       (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  __shared__ cd zl[256];
+  __shared__ uint8_t act[256];
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  PlaneFactor<F> f;
+  f.load(fac, fbase, G.sx, G.sy, threadIdx.x >> 2, threadIdx.x & 3);  // overlaps the vector loads
+  const int l = threadIdx.x;
+  cd rv = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
+  uint8_t ac = 0;
+  if (l < G.S) {
+    const size_t p = (size_t)u.t * G.S + l;
+    ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
+    if (ac) {
+      const cd pv = ld(a.p_new, base + l);
+      st(a.x, base + l, cfma(alpha, pv, ld(a.x, base + l)));
+      rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
+    }
+    st(a.r, base + l, rv);
+    rr.x = cabs2(rv);
+  }
+  act[l] = ac;
+  zl[l] = rv;
+  plane_tile_solve<F>(f, fac, fbase, zl, act, G.sx, G.sy, G.t);
+  cd rz = cmk(0.0, 0.0);
+  if (l < G.S) {
+    const cd zv = ac ? zl[l] : cmk(0.0, 0.0);
+    st(a.z, base + l, zv);
+    rz = cmul(rv, zv);
+  }
+  block_sum2(rz, rr);
+  if (threadIdx.x == 0) {
+    const size_t q = ((size_t)u.k * G.T + u.t) * 2;
+    st(a.partU, q, rz);
+    st(a.partU, q + 1, rr);
+  }
+}
+
 // One workgroup: convergence bookkeeping after launch `it` (it = 0 follows
 // the initialisation) and the number of items still open.
 __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* __restrict__ open) {
@@ -532,16 +795,25 @@ static inline unsigned cocg_blocks(const CocgLaunch& L) {
   return (unsigned)(((size_t)L.K * L.G.T + WAVES - 1) / WAVES);
 }
 
+static inline unsigned planes_blocks(const CocgLaunch& L) {
+  return (unsigned)((size_t)L.K * L.G.T);
+}
+
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
-  const bool regs = L.G.sx <= 16;  // register-resident factors fit 16-site slices
-  if (L.fp16 && regs) k_cocg_init<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
-  else if (L.fp16) k_cocg_init<__half, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
-  else if (L.fp32 && regs) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
-  else if (L.fp32) k_cocg_init<float, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  if (L.G.sx > 16) {  // plane slices: a workgroup per unit
+    if (L.fp16) k_cocg_init_planes<__half><<<planes_blocks(L), 256, 0, s>>>(L, b);
+    else if (L.fp32) k_cocg_init_planes<float><<<planes_blocks(L), 256, 0, s>>>(L, b);
+    else k_cocg_init_planes<double><<<planes_blocks(L), 256, 0, s>>>(L, b);
+    return;
+  }
+  // slices of at most 16 sites: a wave per unit, low-precision factors in registers
+  if (L.fp16) k_cocg_init<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  else if (L.fp32) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
   else k_cocg_init<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
 }
 void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s) {
-  k_cocg_stencil<<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  if (L.G.sx > 16) k_cocg_stencil_planes<<<planes_blocks(L), 256, 0, s>>>(L, it);
+  else k_cocg_stencil<<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
 }
 void launch_prof_collect(unsigned long long* per_item, int n, int classes, int first_class,
                          unsigned long long* tot, hipStream_t s) {
@@ -551,12 +823,14 @@ void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
   k_cocg_check<<<1, 256, 0, s>>>(L, it, open);
 }
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
-  const bool regs = L.G.sx <= 16;
-  if (L.fp16 && regs) k_cocg_update<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
-  else if (L.fp16) k_cocg_update<__half, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
-  else if (L.fp32 && regs)
-    k_cocg_update_occ3<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
-  else if (L.fp32) k_cocg_update<float, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  if (L.G.sx > 16) {
+    if (L.fp16) k_cocg_update_planes<__half><<<planes_blocks(L), 256, 0, s>>>(L, it);
+    else if (L.fp32) k_cocg_update_planes<float><<<planes_blocks(L), 256, 0, s>>>(L, it);
+    else k_cocg_update_planes<double><<<planes_blocks(L), 256, 0, s>>>(L, it);
+    return;
+  }
+  if (L.fp16) k_cocg_update<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  else if (L.fp32) k_cocg_update_occ3<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
   else k_cocg_update<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
 }
 

@@ -90,7 +90,8 @@ def _dense_X_apply(w, d_row, p, level, q):
 
 @pytest.mark.parametrize("dims,s,part", [((32, 32), 16, 0), ((32, 32), 16, 1), ((37, 29), 8, 0),
                                          ((5, 5), 3, 1), ((40,), 8, 0), ((9, 8, 7), 4, 0),
-                                         ((11, 9, 7), 4, 1)])
+                                         ((11, 9, 7), 4, 1), ((12, 11, 10), 6, 0),
+                                         ((11, 10, 9), 5, 1)])
 def test_xmatvec(dims, s, part):
     w = _case(dims, K=2)
     V, om, sig, tV, tom, tsig = device_inputs(w)
@@ -165,6 +166,7 @@ SOLVE_CASES = [
     (_case((9, 8, 7), K=2, mu=1.0), 4, 0),       # cubic lattice (Z = 6), ragged tiles
     (_case((11, 9, 7), K=2, mu=1.0), 4, 1),      # cubic, one level
     (_case((12, 12, 12), K=3, mu=1.0, beta=10.0), 6, 0),  # cubic, 6^3 tiles
+    (_case((13, 11, 10), K=2, mu=1.0), 5, 0),    # cubic, 5^3 tiles (25-site planes), ragged
 ]
 
 
