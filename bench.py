@@ -217,6 +217,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["mixed", "mixed16", "fp64"], default="mixed16")
     ap.add_argument("--workload", choices=["square256", "square128", "small32"], default="square256")
+    ap.add_argument("--inner-tol", type=float, default=1e-14,
+                    help="relative residual of the inner solves")
+    ap.add_argument("--lanczos-tol", type=float, default=1e-11)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the hot kernels with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
@@ -273,6 +276,7 @@ def main():
     tsig = torch.from_numpy(np.ascontiguousarray(sig)).to(dev)
     G = torch.empty((w.n_freq, w.n_sites), dtype=torch.complex128, device=dev)
     plan = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
+                inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
                 profile=0 if args.no_profile else 1)
     log(f"plan: {w.name}, levels={plan.info.levels}, "
         f"max m per level={[plan.info.max_m[l] for l in range(plan.info.levels)]}, "
@@ -359,7 +363,8 @@ def main():
         "config": {"workload": w.name + (", 16x16 subdomains, recursive bisection, full rank"
                                          if part == PART_NESTED else ", 4 subdomains, full rank"),
                    "lattice": list(w.dims), "n_freq": w.n_freq, "beta": w.beta,
-                   "precision": args.precision, "parallelism": "1 GPU"},
+                   "precision": args.precision, "inner_tol": args.inner_tol,
+                   "lanczos_tol": args.lanczos_tol, "parallelism": "1 GPU"},
         "latency_s": {"p50": lat_sorted[len(lat) // 2],
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "max_rel_err_sampled": err,

@@ -88,6 +88,12 @@ typedef struct {
   int profile;        /* 1: time the dominant kernel (inner-solve update) with HIP
                          events on the call's stream; 2: every hot kernel class;
                          algorithmic bytes are counted for all classes [0] */
+  int level_streams;  /* correction levels are independent (each adds its own
+                         diag(X_l)); they run in up to this many concurrent
+                         groups, each on its own HIP stream and workspace,
+                         1 = one after the other, bottom-up.  Results do not
+                         depend on timing; the group sums are added in a fixed
+                         order [4] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */

@@ -37,7 +37,7 @@ class Opts(C.Structure):
     _fields_ = [("leaf_edge", C.c_int), ("partition", C.c_int), ("precision", C.c_int),
                 ("max_rank", C.c_int), ("extra_steps", C.c_int), ("max_inner_iters", C.c_int),
                 ("inner_tol", C.c_double), ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("level_streams", C.c_int)]
 
 
 class Report(C.Structure):
@@ -247,7 +247,7 @@ class Plan:
     def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
                  inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
-                 ctx: "Context | None" = None):
+                 ctx: "Context | None" = None, level_streams=4):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
@@ -255,7 +255,7 @@ class Plan:
             lat.L[a] = dims[a] if a < len(dims) else 1
         lat.t, lat.mu = float(t), float(mu)
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
-                 inner_tol, lanczos_tol, seed, int(profile))
+                 inner_tol, lanczos_tol, seed, int(profile), int(level_streams))
         self.dims = dims
         self.n_sites = 1
         for x in dims:

@@ -82,6 +82,12 @@ struct Work {
   int stat_restarts = 0;
   int stat_capped = 0;      // items stopped by the step cap before exhaustion
   dyson_status pending = DYSON_OK;
+  int kq = 1;               // Lanczos steps the basis Q can hold (Q has kq + 1 vectors)
+  // correction levels run concurrently: groups 1.. of the plan's level
+  // groups run in these workspaces on their own streams (group 0 runs here)
+  std::vector<std::unique_ptr<Work>> sub;
+  std::vector<hipStream_t> sub_stream;
+  hipEvent_t ev = nullptr;
 };
 
 }  // namespace dyson
@@ -127,7 +133,11 @@ struct Slice {
   double* G;
 };
 
-// Device bytes a Work for K frequencies of the plan holds.
+// Correction levels per concurrent group: group 0 holds the level with the
+// longest Lanczos run; within a group levels run bottom-up.
+std::vector<std::vector<int>> level_groups(const dyson_plan* p);
+
+// Device bytes a Work for K frequencies of the plan holds (with its groups).
 size_t work_bytes(const dyson_plan* p, int K);
 dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s);
 void free_work(Work* w, hipStream_t s);

@@ -23,6 +23,7 @@ dyson_opts default_opts() {
   o.lanczos_tol = 1e-11;
   o.seed = 0x5eedULL;
   o.profile = 0;
+  o.level_streams = 4;
   return o;
 }
 
@@ -39,6 +40,7 @@ dyson_opts merge_opts(const dyson_opts* u) {
   if (u->lanczos_tol > 0) o.lanczos_tol = u->lanczos_tol;
   if (u->seed) o.seed = u->seed;
   o.profile = u->profile;
+  if (u->level_streams) o.level_streams = u->level_streams;
   return o;
 }
 
@@ -67,6 +69,7 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
       opts.precision != DYSON_PREC_MIXED16)
     return "unknown precision";
   if (opts.max_rank < 0 || opts.extra_steps < 0) return "max_rank and extra_steps must be >= 0";
+  if (opts.level_streams < 1 || opts.level_streams > 8) return "level_streams must be in [1, 8]";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
   if (n > (1LL << 28)) return "lattice too large";
 

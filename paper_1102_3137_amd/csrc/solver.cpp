@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dyson.h"
@@ -90,11 +91,14 @@ int step_cap(int m, const dyson_opts& o) {
 
 // Every device buffer of a Work for K frequencies, with its size in bytes.
 // The one table serves allocation and the footprint query.
-std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, int K) {
+// kq = Lanczos steps the basis must hold; sub = workspace of a concurrent
+// level group (it reads the diagonal d and the frequency keys of the main one).
+std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, int K, int kq,
+                                                  bool sub) {
   const HostPlan& P = p->hp;
   const size_t NP = (size_t)P.T * P.S;
   const size_t V = (size_t)K * NP * 16;  // bytes per complex vector
-  const size_t nq = P.levels.empty() ? 1 : (size_t)(p->kcap + 1);
+  const size_t nq = P.levels.empty() ? 1 : (size_t)(kq + 1);
   const size_t fe = (size_t)K * P.T * P.sy * P.sx * P.sx * 2;  // reals per factor set
   const size_t fsz = (P.opts.precision == DYSON_PREC_MIXED)     ? 4
                      : (P.opts.precision == DYSON_PREC_MIXED16) ? 2
@@ -119,10 +123,24 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->d_prof, 64},         {(void**)&w->d_wprof, 4 * ni * 8},
       {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 8},
       {(void**)&w->d_flag, 16}};
+  if (sub) {
+    std::vector<std::pair<void**, size_t>> keep;
+    for (auto& e : t)
+      if (e.first != (void**)&w->d && e.first != (void**)&w->d_fkey &&
+          e.first != (void**)&w->stage_om && e.first != (void**)&w->d_flag)
+        keep.push_back(e);
+    return keep;
+  }
   // mixed plans keep complex128 leaf factors beside the low-precision ones;
   // FP64 plans use the first factor slot for them
   if (P.opts.precision != DYSON_PREC_FP64) t.push_back({(void**)&w->fac64, fe * 8});
   return t;
+}
+
+size_t table_bytes(const std::vector<std::pair<void**, size_t>>& t) {
+  size_t b = 0;
+  for (auto& e : t) b += (e.second + 255) / 256 * 256;
+  return b;
 }
 
 void* dev_alloc(const dyson_ctx* c, size_t n, hipStream_t s) {
@@ -145,19 +163,70 @@ void dev_free(const dyson_ctx* c, void* ptr, hipStream_t s) {
 
 namespace dyson {
 
+std::vector<std::vector<int>> level_groups(const dyson_plan* p) {
+  const HostPlan& P = p->hp;
+  const int L = (int)P.levels.size();
+  const int C = std::max(1, std::min(P.opts.level_streams, L));
+  std::vector<std::vector<int>> g(C);
+  if (C == 1) {
+    for (int l = L - 1; l >= 0; --l) g[0].push_back(l);
+    return g;
+  }
+  // longest processing time first on the sequential Lanczos step count
+  std::vector<int> wt(L), order(L);
+  for (int l = 0; l < L; ++l) {
+    int mx = 0;
+    for (int m : P.levels[l].m) mx = std::max(mx, m);
+    wt[l] = step_cap(mx, P.opts);
+    order[l] = l;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return wt[a] > wt[b]; });
+  std::vector<long long> load(C, 0);
+  for (int l : order) {
+    int best = 0;
+    for (int c = 1; c < C; ++c)
+      if (load[c] < load[best]) best = c;
+    g[best].push_back(l);
+    load[best] += wt[l];
+  }
+  for (auto& v : g) std::sort(v.begin(), v.end(), std::greater<int>());  // bottom-up
+  return g;
+}
+
+namespace {
+
+// Lanczos steps a group's basis must hold.
+int group_kq(const dyson_plan* p, const std::vector<int>& levels) {
+  int kq = 1;
+  for (int l : levels)
+    for (int m : p->hp.levels[l].m) kq = std::max(kq, step_cap(m, p->hp.opts) + 1);
+  return kq;
+}
+
+}  // namespace
+
 size_t work_bytes(const dyson_plan* p, int K) {
   Work tmp;
-  size_t b = 0;
-  for (auto& e : work_table(p, &tmp, K)) b += (e.second + 255) / 256 * 256;
+  size_t b = table_bytes(work_table(p, &tmp, K, p->kcap, false));
+  const auto g = level_groups(p);
+  for (size_t c = 1; c < g.size(); ++c)
+    b += table_bytes(work_table(p, &tmp, K, group_kq(p, g[c]), true));
   return b;
 }
 
 void free_work(Work* w, hipStream_t s) {
   const dyson_ctx* c = w->plan ? w->plan->ctx : nullptr;
-  if (c) {
-    (void)hipSetDevice(c->device);
-    for (void* a : w->allocs) dev_free(c, a, s);
+  if (c) (void)hipSetDevice(c->device);
+  for (size_t i = 0; i < w->sub.size(); ++i) {
+    if (w->sub[i]) free_work(w->sub[i].get(), w->sub_stream[i]);
+    if (w->sub_stream[i]) (void)hipStreamDestroy(w->sub_stream[i]);
   }
+  w->sub.clear();
+  w->sub_stream.clear();
+  if (w->ev) (void)hipEventDestroy(w->ev);
+  w->ev = nullptr;
+  if (c)
+    for (void* a : w->allocs) dev_free(c, a, s);
   w->allocs.clear();
   if (w->h_count) (void)hipHostFree(w->h_count);
   w->h_count = nullptr;
@@ -168,31 +237,64 @@ void free_work(Work* w, hipStream_t s) {
   w->pred.clear();
 }
 
-dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s) {
-  if (w->plan == p && K <= w->Kcap) return DYSON_OK;
-  HIPC(hipSetDevice(p->ctx->device));
-  free_work(w, s);
+namespace {
+
+dyson_status alloc_table(const dyson_plan* p, Work* w, int K, int kq, bool sub, hipStream_t s) {
   w->plan = p;
-  for (auto& e : work_table(p, w, K)) {
+  for (auto& e : work_table(p, w, K, kq, sub)) {
     void* ptr = dev_alloc(p->ctx, e.second ? e.second : 1, s);
-    if (!ptr) {
-      const size_t want = e.second;
-      free_work(w, s);
-      return fail(DYSON_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
-    }
+    if (!ptr) return fail(DYSON_ENOMEM, "device allocation of " + std::to_string(e.second) +
+                                            " bytes failed");
     *e.first = ptr;
     w->allocs.push_back(ptr);
     w->bytes += (e.second + 255) / 256 * 256;
   }
-  if (p->hp.opts.precision == DYSON_PREC_FP64) w->fac64 = (double*)w->fac[0];
+  if (p->hp.opts.precision == DYSON_PREC_FP64 && !sub) w->fac64 = (double*)w->fac[0];
   HIPC(hipMemsetAsync(w->d_wprof, 0, 4 * (size_t)K * p->nmax * sizeof(unsigned long long), s));
   if (hipHostMalloc((void**)&w->h_count, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     w->h_count = nullptr;
-    free_work(w, s);
     return fail(DYSON_ENOMEM, "pinned host allocation failed");
   }
   w->Kcap = K;
+  w->kq = kq;
+  return DYSON_OK;
+}
+
+}  // namespace
+
+dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s) {
+  if (w->plan == p && K <= w->Kcap) return DYSON_OK;
+  HIPC(hipSetDevice(p->ctx->device));
+  free_work(w, s);
+  dyson_status st = alloc_table(p, w, K, p->kcap, false, s);
+  const auto g = level_groups(p);
+  if (st == DYSON_OK && g.size() > 1) {
+    if (hipEventCreateWithFlags(&w->ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      w->ev = nullptr;
+      st = fail(DYSON_EDEVICE, "hipEventCreate failed");
+    }
+    for (size_t c = 1; c < g.size() && st == DYSON_OK; ++c) {
+      w->sub.push_back(std::make_unique<Work>());
+      w->sub_stream.push_back(nullptr);
+      if (hipStreamCreateWithFlags(&w->sub_stream.back(), hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        w->sub_stream.back() = nullptr;
+        st = fail(DYSON_EDEVICE, "hipStreamCreate failed");
+        break;
+      }
+      Work* sw = w->sub.back().get();
+      st = alloc_table(p, sw, K, group_kq(p, g[c]), true, w->sub_stream.back());
+      w->bytes += sw->bytes;
+    }
+  }
+  if (st != DYSON_OK) {
+    const std::string msg = g_err;
+    free_work(w, s);
+    g_err = msg;
+    return st;
+  }
   return DYSON_OK;
 }
 
@@ -390,7 +492,7 @@ struct Run {
     const double brk = 1e-6;  // |r^T r| <= brk |r|^2 would give |q| >= 1e3: redo the item
     int kmax = 0;
     for (int m : HP.levels[level].m) kmax = std::max(kmax, step_cap(m, HP.opts));
-    kmax = std::min(kmax, p->kcap);
+    kmax = std::min(kmax, w->kq);
     std::vector<int> st(n_items), stop(n_items);
     for (int attempt = 0; attempt < 3; ++attempt) {
       // start vector, normalized in the bilinear "norm"
@@ -410,7 +512,7 @@ struct Run {
         cgs2(a, L, j + 1);
         launch_lz_norms(a, K, w->R, s);
         launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, s);
-        if (j + 1 < p->kcap) launch_lz_next(a, K, w->R, Qj(j + 1), s);
+        if (j + 1 < w->kq) launch_lz_next(a, K, w->R, Qj(j + 1), s);
         HIPC(hipGetLastError());
       }
       HIPC(hipMemcpyAsync(stop.data(), w->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -515,28 +617,89 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
     // the leaf factors double as the preconditioner of the deepest B graph
     w->fac_g[0] = (int)P.levels.size();
   }
-  // a5-a9: corrections bottom-up
+  // a5-a9: the corrections.  Each level adds its own diag(X_l); the levels
+  // of a group run bottom-up, the groups concurrently on their own streams.
+  const auto groups = level_groups(p);
+  const int G = (int)groups.size();
+  std::vector<dyson_status> gst(G, DYSON_OK);
+  std::vector<std::string> gerr(G);
+  std::vector<std::vector<int>> lsteps_of(P.levels.size());
+  const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
+  if (G > 1) HIPC(hipEventRecord(w->ev, s));  // d, keys and leaf results are ready
+  auto run_group = [&](int g) {
+    Work* gw = (g == 0) ? w : w->sub[g - 1].get();
+    hipStream_t gs = (g == 0) ? s : w->sub_stream[g - 1];
+    dyson_status st = DYSON_OK;
+    if (g > 0) {
+      (void)hipSetDevice(p->ctx->device);
+      gw->d = w->d;
+      gw->d_fkey = w->d_fkey;
+      gw->pending = DYSON_OK;
+      gw->stat_inner = 0;
+      gw->stat_inner_max = 0;
+      gw->stat_restarts = 0;
+      gw->stat_capped = 0;
+      gw->fac_g[0] = gw->fac_g[1] = -1000;
+      gw->prof.reset();
+      gw->prof.on = w->prof.on;
+      if (hipStreamWaitEvent(gs, w->ev, 0) != hipSuccess ||
+          hipMemsetAsync(gw->gacc, 0, V * sizeof(double), gs) != hipSuccess ||
+          (gw->prof.on &&
+           hipMemsetAsync(gw->d_prof, 0, 8 * sizeof(unsigned long long), gs) != hipSuccess))
+        st = fail(DYSON_EDEVICE, "level group set-up failed");
+    }
+    Run gr{p, gw, K, gs};
+    for (int l : groups[g]) {
+      if (st != DYSON_OK) break;
+      if (abort && abort()) {
+        st = fail(DYSON_ECANCELLED, "cancelled");
+        break;
+      }
+      auto tl = std::chrono::steady_clock::now();
+      st = gr.lanczos_level(l, &lsteps_of[l]);
+      if (verbose) {
+        int lmax = 0;
+        for (int v : lsteps_of[l]) lmax = std::max(lmax, v);
+        std::fprintf(stderr, "[dyson] level %d (group %d): %d domains x %d freqs, max steps %d, %.1f ms\n",
+                     l, g, p->lv[l].n, K, lmax,
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count());
+        std::fflush(stderr);
+      }
+      if (st == DYSON_OK && gw->pending != DYSON_OK) {
+        st = gw->pending;
+        g_err = st == DYSON_ENOCONV ? "inner COCG solve hit max_inner_iters"
+                                    : "Lanczos breakdown persisted after restarts";
+      }
+    }
+    if (hipStreamSynchronize(gs) != hipSuccess && st == DYSON_OK)
+      st = fail(DYSON_EDEVICE, "level group stream failed");
+    gst[g] = st;
+    if (st != DYSON_OK) gerr[g] = g_err;
+  };
+  {
+    std::vector<std::thread> th;
+    for (int g = 1; g < G; ++g) th.emplace_back(run_group, g);
+    run_group(0);
+    for (auto& t : th) t.join();
+  }
+  for (int g = 0; g < G; ++g)
+    if (gst[g] != DYSON_OK) return fail(gst[g], gerr[g]);
+  // fixed order: the main group accumulated into gacc, the others follow
+  if (G > 1) {
+    LzArgs all = run.lz_args(0);  // level 0: one domain over every tile
+    for (int g = 1; g < G; ++g) launch_add_into(all, K, w->sub[g - 1]->gacc, w->gacc, s);
+    HIPC(hipGetLastError());
+  }
   int max_rank_used = 0;
   long long lsteps = 0;
-  const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
-  for (int l = (int)P.levels.size() - 1; l >= 0; --l) {
-    if (abort && abort()) {
-      HIPC(hipStreamSynchronize(s));
-      return fail(DYSON_ECANCELLED, "cancelled");
-    }
-    std::vector<int> steps;
-    auto tl = std::chrono::steady_clock::now();
-    CHECKED(run.lanczos_level(l, &steps));
-    int lmax = 0;
-    for (int v : steps) max_rank_used = std::max(max_rank_used, v), lsteps += v, lmax = std::max(lmax, v);
-    if (verbose) {
-      std::fprintf(stderr, "[dyson] level %d: %d domains x %d freqs, max steps %d, %.1f ms, inner iters so far %lld\n",
-                   l, p->lv[l].n, K, lmax,
-                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count(),
-                   w->stat_inner);
-      std::fflush(stderr);
-    }
-    if (w->pending != DYSON_OK) break;
+  for (auto& v : lsteps_of)
+    for (int x : v) max_rank_used = std::max(max_rank_used, x), lsteps += x;
+  for (int g = 1; g < G; ++g) {
+    Work* sw = w->sub[g - 1].get();
+    w->stat_inner += sw->stat_inner;
+    w->stat_inner_max = std::max(w->stat_inner_max, sw->stat_inner_max);
+    w->stat_restarts += sw->stat_restarts;
+    w->stat_capped += sw->stat_capped;
   }
   // a8: scatter each slice to natural order
   for (int j = 0, k0 = 0; j < n; k0 += sl[j].K, ++j)
@@ -555,17 +718,19 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
     rep->batches = 1;
     rep->hbm_bytes = w->bytes;
     if (w->prof.on) {
-      unsigned long long wb[8];
-      HIPC(hipMemcpy(wb, w->d_prof, sizeof(wb), hipMemcpyDeviceToHost));
-      for (int c = 0; c < 4; ++c) w->prof.bytes[c] = (double)wb[c];
-      for (auto& m : w->prof.marks) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, m.second.first, m.second.second) == hipSuccess)
-          rep->kern_ms[m.first] += ms;
-      }
-      for (int c = 0; c < 4; ++c) {
-        rep->kern_launches[c] = w->prof.launches[c];
-        rep->kern_bytes[c] = w->prof.bytes[c];
+      for (int g = 0; g < G; ++g) {
+        Work* gw = (g == 0) ? w : w->sub[g - 1].get();
+        unsigned long long wb[8];
+        HIPC(hipMemcpy(wb, gw->d_prof, sizeof(wb), hipMemcpyDeviceToHost));
+        for (auto& m : gw->prof.marks) {
+          float ms = 0;
+          if (hipEventElapsedTime(&ms, m.second.first, m.second.second) == hipSuccess)
+            rep->kern_ms[m.first] += ms;
+        }
+        for (int c = 0; c < 4; ++c) {
+          rep->kern_launches[c] += gw->prof.launches[c];
+          rep->kern_bytes[c] += (double)wb[c];
+        }
       }
     }
     rep->t_total_ms =

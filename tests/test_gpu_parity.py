@@ -256,3 +256,14 @@ def test_solve_cubic_24(prec):
     print(f"24^3 prec={prec} err={err:.2e} rep={rep}")
     assert rep["truncated"] == 0
     assert err < 1e-9
+
+
+def test_concurrent_levels_match_sequential():
+    """The correction levels are independent; running them in concurrent
+    groups changes only the order in which the group sums are added."""
+    w = _case((96, 80), K=5, beta=20.0)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    G1 = _plan(w, 16, 0, 2, level_streams=1).solve(tV, tom, tsig).cpu().numpy()
+    G4 = _plan(w, 16, 0, 2, level_streams=4).solve(tV, tom, tsig).cpu().numpy()
+    assert oracle.rel_err(G4, G1) < 1e-13
+    assert oracle.rel_err(G4, oracle_G(w, V, om, sig)) < 1e-10
