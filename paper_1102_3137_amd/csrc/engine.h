@@ -60,7 +60,7 @@ struct Work {
   double* partial = nullptr;
   double *hpart = nullptr, *h = nullptr;
   CocgState cst{};
-  int *lz_stopped = nullptr, *lz_steps = nullptr;
+  int *lz_stopped = nullptr, *lz_steps = nullptr, *lz_reorth = nullptr;
   double* Dl = nullptr;  // diagonal correction of the level being run
   double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
          *lz_scal = nullptr;

@@ -73,6 +73,7 @@ struct LzArgs {
   int n_items;
   unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (CGS update,
                              // CGS products) booked by each item's lead block, or null
+  int* reorth;      // [n_items] 1 if the second Gram-Schmidt pass runs for the item
 };
 
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
@@ -107,12 +108,16 @@ void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, 
 void launch_lz_alpha(const LzArgs& a, int K, const double* q, const double* u, hipStream_t s);
 void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qprev, const double* u,
                      double* r, double* D, hipStream_t s);
+// Gram-Schmidt pass `pass` (0: always; 1: only items whose reorth flag is set)
 void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
-                    const double* r, hipStream_t s);
-void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
+                    const double* r, int pass, hipStream_t s);
+void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec, int pass,
                        hipStream_t s);
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
-                       double* D, hipStream_t s);
+                       double* D, int pass, hipStream_t s);
+// After pass 0: reorth[item] = |r'|^2 < eta2 |r|^2 (the pass removed a large part of r)
+void launch_cgs_decide(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
+                       double eta2, hipStream_t s);
 void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s);
 void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s);
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,

@@ -342,10 +342,13 @@ __global__ __launch_bounds__(256) void k_lz_recur(LzArgs a, const double* __rest
 
 // Classical Gram-Schmidt, bilinear: h_i = Q_i^T r for i < nvec.  Each wave
 // takes every fourth basis vector of the tile; lanes cover 4 sites each.
+// Pass 0 also records the partial |r|^2 (slot nvec); pass 1 runs only for
+// the items the selective test flagged.
 __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restrict__ Q,
                                                  size_t qstride, int nvec,
-                                                 const double* __restrict__ r) {
+                                                 const double* __restrict__ r, int pass) {
   LZ_ITEM();
+  if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
@@ -358,6 +361,13 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
     rl[c] = (l < G.S) ? ld(r, base + l) : cmk(0.0, 0.0);
   }
   double* out = a.hpart + ((size_t)k * G.T + t) * (size_t)a.hstride * 2;
+  if (pass == 0 && wv == 0) {
+    double rr = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rr += cabs2(rl[c]);
+    const cd s2 = wave_sum(cmk(rr, 0.0));
+    if (lane == 0) st(out, nvec, s2);
+  }
   for (int i = wv; i < nvec; i += 4) {
     const double* qi = Q + (size_t)i * qstride;
     cd acc = cmk(0.0, 0.0);
@@ -371,13 +381,16 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   }
 }
 
-// h[item][i] = sum over the domain's tiles of the partials (fixed order)
+// h[item][i] = sum over the domain's tiles of the partials (fixed order);
+// pass 0 also sums |r|^2 into h[item][nvec]
 __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
-                             const int* __restrict__ thi, int nvec) {
+                             const int* __restrict__ thi, int nvec, int pass) {
   const int item = blockIdx.y;
   const int k = item / a.n_nodes, node = item % a.n_nodes;
   if (a.stopped[item]) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += gridDim.x * blockDim.x) {
+  if (pass == 1 && !a.reorth[item]) return;
+  const int n = (pass == 0) ? nvec + 1 : nvec;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     cd s = cmk(0.0, 0.0);
     for (int t = tlo[node]; t < thi[node]; ++t)
       s = cadd(s, ld(a.hpart + ((size_t)k * a.G.T + t) * (size_t)a.hstride * 2, i));
@@ -389,10 +402,13 @@ __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
 // re-orthogonalization the matrix of X in the computed basis is the
 // Hessenberg H = T + (re-orthogonalization coefficients); its column j
 // above the tridiagonal band is added here so that diag(Q H Q^T) is formed.
+// Pass 0 records the partial |r'|^2 of the updated r for the selective test.
 __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __restrict__ Q,
                                                     size_t qstride, int nvec,
-                                                    double* __restrict__ r, double* __restrict__ D) {
+                                                    double* __restrict__ r, double* __restrict__ D,
+                                                    int pass) {
   LZ_ITEM();
+  if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
   if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
     a.wctr[item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
@@ -402,15 +418,38 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
   for (int i = threadIdx.x; i < nvec && i < 1024; i += blockDim.x) hl[i] = ld(hs, i);
   __syncthreads();
   const int tid = threadIdx.x;
-  if (tid >= G.S) return;
-  cd acc = cmk(0.0, 0.0);
-  for (int i = 0; i < nvec; ++i) {
-    const cd hv = (i < 1024) ? hl[i] : ld(hs, i);
-    acc = cfma(hv, ld(Q + (size_t)i * qstride, base + tid), acc);
+  double rr = 0.0;
+  if (tid < G.S) {
+    cd acc = cmk(0.0, 0.0);
+    for (int i = 0; i < nvec; ++i) {
+      const cd hv = (i < 1024) ? hl[i] : ld(hs, i);
+      acc = cfma(hv, ld(Q + (size_t)i * qstride, base + tid), acc);
+    }
+    const cd rn = csub(ld(r, base + tid), acc);
+    st(r, base + tid, rn);
+    rr = cabs2(rn);
+    const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
+    st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
   }
-  st(r, base + tid, csub(ld(r, base + tid), acc));
-  const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
-  st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
+  if (pass == 0) {
+    cd s0 = cmk(rr, 0.0), s1 = cmk(0.0, 0.0);
+    block_sum2(s0, s1);
+    if (tid == 0) st(a.partial, ((size_t)k * G.T + t) * 2, s0);
+  }
+}
+
+// Selective second pass (Daniel, Gragg, Kaufman and Stewart, 1976): repeat
+// the projection only when the first one removed most of r.
+__global__ void k_cgs_decide(LzArgs a, int K, const int* __restrict__ tlo,
+                             const int* __restrict__ thi, int nvec, double eta2) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= K * a.n_nodes) return;
+  if (a.stopped[item]) return;
+  const int k = item / a.n_nodes, node = item % a.n_nodes;
+  double r1 = 0.0;
+  for (int t = tlo[node]; t < thi[node]; ++t) r1 += a.partial[((size_t)k * a.G.T + t) * 4];
+  const double r0 = a.h[((size_t)item * a.hstride + nvec) * 2];
+  a.reorth[item] = (r1 < eta2 * r0) ? 1 : 0;
 }
 
 // partials |r|^2 and r^T r
@@ -583,17 +622,22 @@ void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qpre
   k_lz_recur<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, qprev, u, r, D);
 }
 void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
-                    const double* r, hipStream_t s) {
-  k_cgs_dot<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r);
+                    const double* r, int pass, hipStream_t s) {
+  k_cgs_dot<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, pass);
 }
-void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
+void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec, int pass,
                        hipStream_t s) {
-  dim3 grid((nvec + 255) / 256, K * a.n_nodes);
-  k_cgs_reduce<<<grid, 256, 0, s>>>(a, K, tlo, thi, nvec);
+  dim3 grid((nvec + 256) / 256, K * a.n_nodes);
+  k_cgs_reduce<<<grid, 256, 0, s>>>(a, K, tlo, thi, nvec, pass);
 }
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
-                       double* D, hipStream_t s) {
-  k_cgs_update<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, D);
+                       double* D, int pass, hipStream_t s) {
+  k_cgs_update<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, D, pass);
+}
+void launch_cgs_decide(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
+                       double eta2, hipStream_t s) {
+  const int n = K * a.n_nodes;
+  k_cgs_decide<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, nvec, eta2);
 }
 void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s) {
   k_lz_norms<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r);

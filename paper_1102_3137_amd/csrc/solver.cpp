@@ -117,6 +117,7 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->cst.bn2, ni * 8},   {(void**)&w->rho2, ni * 32},
       {(void**)&w->partS, (size_t)K * P.T * 16},
       {(void**)&w->lz_stopped, ni * 4}, {(void**)&w->lz_steps, ni * 4},
+      {(void**)&w->lz_reorth, ni * 4},
       {(void**)&w->lz_alpha, ni * 16},  {(void**)&w->lz_beta, ni * 16},
       {(void**)&w->lz_unorm2, ni * 8},  {(void**)&w->lz_umax2, ni * 8},
       {(void**)&w->lz_scal, ni * 16},   {(void**)&w->d_count, 16},
@@ -444,6 +445,7 @@ struct Run {
     a.thi = p->lv[level].thi;
     a.n_items = K * p->lv[level].n;
     a.wctr = w->prof.on ? w->d_wprof + 2 * (size_t)K * p->nmax : nullptr;
+    a.reorth = w->lz_reorth;
     return a;
   }
 
@@ -467,12 +469,16 @@ struct Run {
     return DYSON_OK;
   }
 
+  // Full re-orthogonalization of r against the basis: classical Gram-Schmidt,
+  // repeated for the items whose first pass removed most of r (|r'| <
+  // |r| / sqrt 2), which keeps the basis orthogonal to working precision.
   void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
-      timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, s); });
-      launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, s);
-      timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, w->Dl, s); });
+      timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, pass, s); });
+      launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, pass, s);
+      timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, w->Dl, pass, s); });
+      if (pass == 0) launch_cgs_decide(a, K, L.tlo, L.thi, nvec, 0.5, s);
     }
   }
 
