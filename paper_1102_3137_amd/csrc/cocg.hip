@@ -285,6 +285,22 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   const size_t kb = (size_t)u.k * NP;
   const size_t base = kb + (size_t)u.t * G.S;
   const bool lead = u.t == a.tlo[u.node];  // records the item state
+  // the tile's own p_old and z do not depend on beta: their loads go out
+  // before the item reduction, so the two latencies overlap
+  bool ac[4];
+  cd po[4], zo[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    ac[e] = false;
+    po[e] = zo[e] = cmk(0.0, 0.0);
+    if (l < G.S) {
+      const size_t p = (size_t)u.t * G.S + l;
+      ac[e] = active(G.kind[p], G.depth[p], a.g);
+      po[e] = ld(a.p_old, base + l);
+      zo[e] = ld(a.z, base + l);
+    }
+  }
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
     cd rho, rr;
@@ -307,19 +323,12 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
         ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
   __shared__ cd psh[WAVES][256];
   cd* pl = psh[u.wave];
-  bool ac[4];
   cd pn[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int l = u.lane + 64 * e;
-    ac[e] = false;
-    pn[e] = cmk(0.0, 0.0);
-    if (l < G.S) {
-      const size_t p = (size_t)u.t * G.S + l;
-      ac[e] = active(G.kind[p], G.depth[p], a.g);
-      if (ac[e]) pn[e] = cfma(beta, ld(a.p_old, base + l), ld(a.z, base + l));
-      st(a.p_new, base + l, pn[e]);
-    }
+    pn[e] = ac[e] ? cfma(beta, po[e], zo[e]) : cmk(0.0, 0.0);
+    if (l < G.S) st(a.p_new, base + l, pn[e]);
     pl[l] = pn[e];
   }
   wave_sync();
@@ -339,10 +348,11 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
       if (nt == u.t) {
         nb = cadd(nb, pl[nl]);  // inactive sites hold 0 in pl
       } else {
-        // p_new at a site of a neighbouring tile (the same domain when active)
+        // p_new at a site of a neighbouring tile (the same domain when
+        // active); its values are read with the flags and masked after
         const size_t np = (size_t)nt * G.S + nl;
-        if (active(G.kind[np], G.depth[np], a.g))
-          nb = cadd(nb, cfma(beta, ld(a.p_old, kb + np), ld(a.z, kb + np)));
+        const cd pv = ld(a.p_old, kb + np), zv = ld(a.z, kb + np);
+        if (active(G.kind[np], G.depth[np], a.g)) nb = cadd(nb, cfma(beta, pv, zv));
       }
     }
     const cd sv = cfma(ld(a.d, base + l), pn[e], cscale(nb, G.t));
@@ -361,6 +371,10 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   if (!u.ok || a.st.done[u.item]) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  WaveFactor<F, REG> f;
+  f.load(fac, fbase, G.sx, G.sy, u.lane);  // issued first: overlaps the item reduction
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
@@ -378,10 +392,6 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   cd* zl = zsh[u.wave];
   cd* rl = rsh[u.wave];
   uint8_t* act = ash[u.wave];
-  const F* fac = (const F*)a.fac;
-  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
-  WaveFactor<F, REG> f;
-  f.load(fac, fbase, G.sx, G.sy, u.lane);  // issued early: overlaps the vector traffic
   cd rr = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
