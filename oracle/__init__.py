@@ -20,10 +20,11 @@ marks a function with no independent pin (none at present).
 """
 from .dyson import (assemble_diag, hamiltonian, dense_hamiltonian, diag_inv_dense,
                     diag_inv_rgf, diag_inv_sampled, closed_form_periodic,
-                    closed_form_open_uniform, oracle_diag, rel_err)
+                    closed_form_open_uniform, closed_form_uniform, oracle_diag, rel_err)
 from .lowrank import lowrank_diag, separator_positions, plan_boxes
 
 __all__ = ["assemble_diag", "hamiltonian", "dense_hamiltonian", "diag_inv_dense",
            "diag_inv_rgf", "diag_inv_sampled", "closed_form_periodic",
-           "closed_form_open_uniform", "oracle_diag", "rel_err", "lowrank_diag",
+           "closed_form_open_uniform", "closed_form_uniform", "oracle_diag", "rel_err",
+           "lowrank_diag",
            "separator_positions", "plan_boxes"]

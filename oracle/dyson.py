@@ -39,9 +39,11 @@ def _bonds(dims, periodic=False):
     """Nearest-neighbour bonds (i, j), i < j in natural order (x fastest).
 
     Z = 2 D neighbours per interior site: 4 on the square lattice, 6 on the
-    cubic one (Sec. I).  With periodic=True the lattice wraps (used only by the
-    closed-form pin of a uniform periodic lattice)."""
+    cubic one (Sec. I).  periodic: True wraps every axis, or one flag per axis
+    (a wrapped axis adds the bond between sites L-1 and 0)."""
     dims = tuple(int(L) for L in dims)
+    per = ([bool(periodic)] * len(dims) if np.ndim(periodic) == 0
+           else [bool(x) for x in periodic])
     n = int(np.prod(dims))
     idx = np.arange(n).reshape(dims[::-1])          # [..., y, x]
     rows, cols = [], []
@@ -52,7 +54,7 @@ def _bonds(dims, periodic=False):
             continue
         src = idx
         dst = np.roll(idx, -1, axis=ax)
-        if not periodic:
+        if not per[a]:
             sl = [slice(None)] * len(dims)
             sl[ax] = slice(0, L - 1)
             src, dst = src[tuple(sl)], dst[tuple(sl)]
@@ -154,6 +156,36 @@ def closed_form_periodic(dims, z, t):
     for g in grids:
         eps = (eps[:, None] + g[None, :]).ravel()
     return np.mean(1.0 / (z + t * eps))
+
+
+def closed_form_uniform(dims, z, t, periodic):
+    """Uniform lattice, constant diagonal z, each axis periodic or open: H is a
+    sum over axes of commuting chain operators, so its eigenvectors are products
+    of chain modes.  A periodic axis contributes plane waves (|psi_k(x)|^2 = 1/L,
+    eigenvalue 2cos(2 pi k/L)), an open axis the sine modes of
+    closed_form_open_uniform, and G_ii = sum over modes of the product of the
+    squared mode values at site i over (z + t * sum of eigenvalues).
+    Returns G_ii for all sites in natural order."""
+    dims = tuple(int(L) for L in dims)
+    wts, lams = [], []
+    for L, p in zip(dims, periodic):
+        x = np.arange(L)
+        if p and L > 2:
+            k = np.arange(L)
+            wts.append(np.full((L, L), 1.0 / L))
+            lams.append(2.0 * np.cos(2.0 * np.pi * k / L))
+        else:
+            n = np.arange(1, L + 1)
+            wts.append((2.0 / (L + 1)) * np.sin(np.pi * np.outer(x + 1, n) / (L + 1)) ** 2)
+            lams.append(2.0 * np.cos(np.pi * n / (L + 1)))
+    out = np.zeros(tuple(dims), dtype=np.complex128)
+    for modes in itertools.product(*[range(L) for L in dims]):
+        lam = sum(lams[a][modes[a]] for a in range(len(dims)))
+        w = wts[0][:, modes[0]]
+        for a in range(1, len(dims)):
+            w = np.multiply.outer(w, wts[a][:, modes[a]])
+        out += w / (z + t * lam)
+    return np.transpose(out).reshape(-1)
 
 
 def closed_form_open_uniform(dims, z, t):

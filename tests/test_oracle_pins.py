@@ -53,6 +53,30 @@ def test_open_uniform_closed_form(dims):
     assert oracle.rel_err(od.diag_inv_rgf(dims, d, -1.0), ref) < 1e-13
 
 
+@pytest.mark.parametrize("dims,per", [((6, 5), (1, 0)), ((5, 7), (0, 1)), ((4, 3, 5), (0, 1, 1)),
+                                      ((3, 4, 3), (1, 0, 1)), ((8,), (1,))])
+def test_mixed_boundary_closed_form(dims, per):
+    """Uniform lattice with some axes periodic: the product-of-chain-modes
+    closed form equals O1 with per-axis wrap bonds; a wrong axis flag fails."""
+    n = int(np.prod(dims))
+    z = 0.35 + 0.29j
+    d = np.full(n, z)
+    ref = oracle.closed_form_uniform(dims, z, -1.0, per)
+    assert oracle.rel_err(od.diag_inv_dense(dims, d, -1.0, periodic=per), ref) < 1e-12
+    wrong = tuple(1 - p for p in per)
+    assert oracle.rel_err(od.diag_inv_dense(dims, d, -1.0, periodic=wrong), ref) > 1e-3
+
+
+def test_uniform_closed_form_reduces_to_the_pure_cases():
+    """All axes periodic or all open: the mixed closed form gives the same
+    numbers as the two separate closed forms."""
+    dims, z = (5, 4, 3), 0.1 + 0.4j
+    G = oracle.closed_form_uniform(dims, z, 0.8, (1, 1, 1))
+    assert np.max(np.abs(G - oracle.closed_form_periodic(dims, z, 0.8))) < 1e-13
+    G = oracle.closed_form_uniform(dims, z, 0.8, (0, 0, 0))
+    assert oracle.rel_err(G, oracle.closed_form_open_uniform(dims, z, 0.8)) < 1e-13
+
+
 def test_odd_periodic_sees_hopping_sign():
     """On a non-bipartite (odd periodic) lattice the sign of t is observable:
     the oracle must follow H_ij = +t (eq. (1)), not -t."""
