@@ -54,12 +54,16 @@ typedef enum {
 } dyson_status;
 
 /* Lattice geometry and hopping (eq. (1)): chain, square (Z=4) or simple
- * cubic (Z=6) lattice.  Open boundaries only. */
+ * cubic (Z=6) lattice.  periodic[a] = 1 wraps axis a (bond between sites
+ * L_a - 1 and 0); such an axis needs L_a >= 3 and L_a a multiple of the leaf
+ * edge, and its wrap plane (sites at coordinate L_a - 1) joins the interface
+ * of the top correction level, which leaves every subdomain open. */
 typedef struct {
-  int dim;       /* 1, 2 or 3 */
-  int L[3];      /* extents, unused axes = 1; x fastest */
-  double t;      /* hopping: H_ij = t on each nearest-neighbour bond */
-  double mu;     /* chemical potential in H_ii */
+  int dim;         /* 1, 2 or 3 */
+  int L[3];        /* extents, unused axes = 1; x fastest */
+  int periodic[3]; /* 0 open, 1 periodic; unused axes 0 */
+  double t;        /* hopping: H_ij = t on each nearest-neighbour bond */
+  double mu;       /* chemical potential in H_ii */
 } dyson_lattice;
 
 enum { DYSON_PART_NESTED = 0, DYSON_PART_SINGLE = 1 };

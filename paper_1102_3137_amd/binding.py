@@ -30,7 +30,8 @@ class DysonError(RuntimeError):
 
 
 class Lattice(C.Structure):
-    _fields_ = [("dim", C.c_int), ("L", C.c_int * 3), ("t", C.c_double), ("mu", C.c_double)]
+    _fields_ = [("dim", C.c_int), ("L", C.c_int * 3), ("periodic", C.c_int * 3),
+                ("t", C.c_double), ("mu", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -247,12 +248,14 @@ class Plan:
     def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
                  inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
-                 ctx: "Context | None" = None, level_streams=4):
+                 ctx: "Context | None" = None, level_streams=4, periodic=None):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
+        per = tuple(periodic) if periodic is not None else (0,) * len(dims)
         for a in range(3):
             lat.L[a] = dims[a] if a < len(dims) else 1
+            lat.periodic[a] = int(per[a]) if a < len(per) else 0
         lat.t, lat.mu = float(t), float(mu)
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
                  inner_tol, lanczos_tol, seed, int(profile), int(level_streams))

@@ -57,6 +57,8 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   for (int a = 0; a < 3; ++a) {
     if (lat.L[a] < 1) return "lattice extents must be >= 1";
     if (a >= lat.dim && lat.L[a] != 1) return "unused lattice axes must have extent 1";
+    if (lat.periodic[a] != 0 && lat.periodic[a] != 1) return "periodic flags must be 0 or 1";
+    if (a >= lat.dim && lat.periodic[a]) return "unused lattice axes cannot be periodic";
   }
   if (!std::isfinite(lat.t) || !std::isfinite(lat.mu)) return "t and mu must be finite";
   const int smax = (lat.dim == 3) ? 6 : 16;
@@ -73,9 +75,12 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
   if (n > (1LL << 28)) return "lattice too large";
 
+  for (int a = 0; a < lat.dim; ++a)
+    if (lat.periodic[a] && (lat.L[a] < 3 || lat.L[a] % opts.leaf_edge != 0))
+      return "a periodic axis needs L >= 3 and L a multiple of leaf_edge";
   P = HostPlan{};
   P.dim = lat.dim;
-  for (int a = 0; a < 3; ++a) P.L[a] = lat.L[a];
+  for (int a = 0; a < 3; ++a) P.L[a] = lat.L[a], P.periodic[a] = lat.periodic[a];
   P.t = lat.t;
   P.mu = lat.mu;
   P.opts = opts;
@@ -95,32 +100,37 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   P.N = (int)n;
 
   // site coordinate range of a tile box along axis a; the high fringe belongs
-  // to an ancestor separator unless the box reaches the lattice edge
+  // to an ancestor separator unless the box reaches an open lattice edge (on
+  // a periodic axis the last plane is the top level's wrap separator)
   auto range = [&](const Box& b, int a, int& lo, int& hi) {
     if (a >= D) { lo = 0; hi = 1; return; }
     lo = s * b.lo[a];
-    hi = (b.hi[a] < TT[a]) ? s * b.hi[a] - 1 : P.L[a];
+    hi = (b.hi[a] < TT[a] || P.periodic[a]) ? s * b.hi[a] - 1 : P.L[a];
   };
 
   struct Node {
     Box box;
     int level;
     std::vector<int> split[3];  // tile boundaries i: separator plane at s*i-1
+    bool wrap[3] = {false, false, false};  // top level: plane L-1 of a periodic axis
     std::vector<int> children;
   };
   std::vector<Node> nodes;
   std::function<int(Box, int)> rec = [&](Box b, int level) -> int {
     int id = (int)nodes.size();
-    nodes.push_back(Node{b, level, {}, {}});
+    nodes.push_back(Node{b, level, {}, {false, false, false}, {}});
     std::vector<int> cand[3];
-    bool any = false;
+    bool any = false, wrap = false;
     for (int a = 0; a < 3; ++a) {
       for (int i = b.lo[a] + 1; i < b.hi[a]; ++i) cand[a].push_back(i);
       any |= !cand[a].empty();
+      if (level == 0 && a < D && P.periodic[a]) nodes[id].wrap[a] = wrap = true;
     }
-    if (!any) return id;
+    if (!any && !wrap) return id;
     std::vector<int> sp[3];
-    if (opts.partition == DYSON_PART_SINGLE) {
+    if (!any) {
+      // only wrap planes: the one child is the same tile box, now open
+    } else if (opts.partition == DYSON_PART_SINGLE) {
       for (int a = 0; a < 3; ++a) sp[a] = cand[a];
     } else {
       int best_axis = -1, best_ext = -1;
@@ -190,6 +200,7 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
       for (int sgn = 0; sgn < 2; ++sgn) {
         int h[3] = {g[0], g[1], g[2]};
         h[a] += sgn ? 1 : -1;
+        if (a < D && P.periodic[a]) h[a] = (h[a] + TT[a]) % TT[a];  // wrap bond
         if (h[a] < 0 || h[a] >= TT[a]) continue;
         P.nbr[t * 6 + 2 * a + sgn] = tile_of_grid[gidx(h[0], h[1], h[2])];
       }
@@ -232,7 +243,10 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
   for (int id : order) {
     const Node& nd = nodes[id];
     int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) range(nd.box, a, lo[a], hi[a]);
+    for (int a = 0; a < 3; ++a) {
+      range(nd.box, a, lo[a], hi[a]);
+      if (nd.wrap[a]) hi[a] = P.L[a];  // the top level owns the wrap plane
+    }
     const bool leaf = nd.children.empty();
     int m = 0;
     for (int z = lo[2]; z < hi[2]; ++z)
@@ -240,8 +254,10 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
         for (int x = lo[0]; x < hi[0]; ++x) {
           const int c[3] = {x, y, z};
           bool on = false;
-          for (int a = 0; a < 3 && !leaf; ++a)
+          for (int a = 0; a < 3 && !leaf; ++a) {
             for (int i : nd.split[a]) on |= (c[a] == s * i - 1);
+            on |= nd.wrap[a] && c[a] == P.L[a] - 1;
+          }
           const int i = x + Lx * (y + Ly * z);
           if ((!leaf && !on) || claimed[i]) continue;
           claimed[i] = 1;

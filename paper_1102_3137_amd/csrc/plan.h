@@ -4,9 +4,10 @@
 // p < L-1 (the Fig. 1 layout generalised to any size), so every subdomain
 // ("leaf") spans at most s-1 sites per axis (s at the last tile).  A tile is
 // the s x s block of the lattice holding one leaf plus the separator sites
-// on its high-x / high-y fringe.  Tiles are numbered in depth-first order of
-// the domain tree, so every domain of every level owns a contiguous range
-// of tiles.
+// on its high-x / high-y fringe.  On a periodic axis the plane at L-1 (one
+// end of the wrap bonds) is a separator of the top level as well.  Tiles are
+// numbered in depth-first order of the domain tree, so every domain of every
+// level owns a contiguous range of tiles.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -28,6 +29,7 @@ struct LevelTable {
 struct HostPlan {
   int dim = 2;
   int L[3] = {1, 1, 1};
+  int periodic[3] = {0, 0, 0};
   double t = -1.0, mu = 0.0;
   dyson_opts opts{};
   int s = 16;         // leaf edge

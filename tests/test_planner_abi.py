@@ -34,8 +34,10 @@ def _host_plan(dims, s, part, **kw):
     lat.dim = len(dims)
     if len(dims) > 3:
         raise B.DysonError(1, "at most three axes")
+    per = kw.get("periodic", (0,) * len(dims))
     for a in range(3):
         lat.L[a] = dims[a] if a < len(dims) else 1
+        lat.periodic[a] = per[a] if a < len(per) else 0
     lat.t, lat.mu = -1.0, 0.5
     o = B.Opts(s, part, kw.get("precision", 0), kw.get("max_rank", 0), 10, 2000, 1e-14, 1e-11,
                1, 0)
@@ -136,3 +138,33 @@ def test_serving_entry_points_reject_null_handles():
     assert lib.dyson_submit(plan, 1, None, None, None, None, 0, B.C.byref(h)) == B.EINVAL
     assert b"device context" in lib.dyson_last_error()
     B.dyson_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("dims,s,part,per", [((32, 32), 16, 0, (1, 1)), ((48, 32), 8, 0, (1, 0)),
+                                             ((16, 24), 8, 1, (0, 1)), ((12, 12, 12), 6, 0, (1, 1, 1)),
+                                             ((16, 8), 8, 0, (1, 1)), ((24,), 8, 0, (1,))])
+def test_periodic_plan_separates_every_leaf(dims, s, part, per):
+    """With wrap bonds, the separator set must still cut the lattice into
+    leaves: no bond of the periodic lattice joins two leaf sites of different
+    tiles, and the wrap planes belong to the top level."""
+    from oracle import dyson as od
+    plan = _host_plan(dims, s, part, periodic=per)
+    n = int(np.prod(dims))
+    depth, is_sep, tile = B.dyson_plan_get_maps(plan, n)
+    B.dyson_plan_destroy(plan)
+    r, c = od._bonds(dims, per)
+    both_leaf = (is_sep[r] == 0) & (is_sep[c] == 0)
+    assert np.all(tile[r][both_leaf] == tile[c][both_leaf])
+    coords = np.stack(np.unravel_index(np.arange(n), dims[::-1])[::-1], axis=1)
+    for a, p in enumerate(per):
+        if p:
+            on = coords[:, a] == dims[a] - 1
+            assert np.all(is_sep[on] == 1) and np.all(depth[on] == 0)
+
+
+@pytest.mark.parametrize("dims,s,per", [((30, 32), 16, (1, 0)), ((2,), 2, (1,)), ((8, 8), 4, (0, 2)),
+                                        ((8, 1), 4, (0, 1))])
+def test_periodic_plan_rejects_invalid(dims, s, per):
+    with pytest.raises(B.DysonError) as e:
+        _host_plan(dims, s, B.PART_NESTED, periodic=per)
+    assert e.value.status == 1
