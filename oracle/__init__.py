@@ -18,12 +18,12 @@ lowrank  -- a plain mirror of the paper's Lanczos-based low-rank correction
 Every function cites the passage of the paper it follows.  "parity unpinned"
 marks a function with no independent pin (none at present).
 """
-from .dyson import (assemble_diag, hamiltonian, dense_hamiltonian, diag_inv_dense,
+from .dyson import (assemble_diag, assemble_diag_z, hamiltonian, dense_hamiltonian, diag_inv_dense,
                     diag_inv_rgf, diag_inv_sampled, closed_form_periodic,
                     closed_form_open_uniform, closed_form_uniform, oracle_diag, rel_err)
 from .lowrank import lowrank_diag, separator_positions, plan_boxes
 
-__all__ = ["assemble_diag", "hamiltonian", "dense_hamiltonian", "diag_inv_dense",
+__all__ = ["assemble_diag", "assemble_diag_z", "hamiltonian", "dense_hamiltonian", "diag_inv_dense",
            "diag_inv_rgf", "diag_inv_sampled", "closed_form_periodic",
            "closed_form_open_uniform", "closed_form_uniform", "oracle_diag", "rel_err",
            "lowrank_diag",

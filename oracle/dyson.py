@@ -35,6 +35,16 @@ def assemble_diag(V, omega, sigma, mu):
     return (1j * omega[:, None] + mu) - V[None, :] - sigma
 
 
+def assemble_diag_z(V, z, sigma, mu):
+    """eq. (1) at complex energies z_k (Im z_k > 0) in place of i w_k, e.g. the
+    real axis z_k = w_k + i eta (Sec. I notes the same matrix there):
+    d_i(k) = z_k + mu - V_i - Sigma_i(z_k).  z [K] complex."""
+    V = np.asarray(V, dtype=np.float64)
+    z = np.asarray(z, dtype=np.complex128)
+    sigma = np.asarray(sigma, dtype=np.complex128)
+    return (z[:, None] + mu) - V[None, :] - sigma
+
+
 def _bonds(dims, periodic=False):
     """Nearest-neighbour bonds (i, j), i < j in natural order (x fastest).
 

@@ -77,6 +77,26 @@ def test_uniform_closed_form_reduces_to_the_pure_cases():
     assert oracle.rel_err(G, oracle.closed_form_open_uniform(dims, z, 0.8)) < 1e-13
 
 
+def test_complex_energy_assembly():
+    """eq. (1) at z = i w is the Matsubara assembly; at a real-axis energy the
+    dense inverse of a uniform periodic lattice meets the plane-wave closed
+    form, and Im G < 0 (retarded)."""
+    dims = (6, 5)
+    n = 30
+    rng = np.random.default_rng(4)
+    V = rng.uniform(0, 1, n)
+    om = np.array([0.3, 1.1])
+    sig = rng.uniform(-0.2, 0.2, (2, n)) + 1j * rng.uniform(-0.2, 0.0, (2, n))
+    assert np.array_equal(oracle.assemble_diag_z(V, 1j * om, sig, 0.4),
+                          oracle.assemble_diag(V, om, sig, 0.4))
+    z = np.array([-0.7 + 0.05j])
+    d = oracle.assemble_diag_z(np.zeros(n), z, np.zeros((1, n)), 0.5)[0]
+    G = od.diag_inv_dense(dims, d, -1.0, periodic=True)
+    ref = oracle.closed_form_periodic(dims, z[0] + 0.5, -1.0)
+    assert np.max(np.abs(G - ref)) / abs(ref) < 1e-12
+    assert np.all(G.imag < 0)
+
+
 def test_odd_periodic_sees_hopping_sign():
     """On a non-bipartite (odd periodic) lattice the sign of t is observable:
     the oracle must follow H_ij = +t (eq. (1)), not -t."""
