@@ -26,9 +26,10 @@
  *     output buffers are left untouched or partially written and must not
  *     be used; dyson_last_error() gives a message (thread-local).
  *   - Validation returns DYSON_EINVAL: dim not in {1,2,3}, any L < 1, K < 1,
- *     w_k <= 0, non-finite input, or Im(i w_k - Sigma_i) <= 0 (the last
- *     keeps Im H positive definite, so H and every principal submatrix are
- *     non-singular and the pivot-free factorizations below exist).
+ *     w_k <= 0 (Im z_k <= 0), non-finite input, or Im(i w_k - Sigma_i) <= 0
+ *     (Im(z_k - Sigma_i) <= 0); the last keeps Im H positive definite, so H
+ *     and every principal submatrix are non-singular and the pivot-free
+ *     factorizations below exist.
  */
 #ifndef DYSON_MI355X_H
 #define DYSON_MI355X_H
@@ -191,6 +192,15 @@ dyson_status dyson_solve(dyson_plan* plan, int K, const double* d_V,
                          const double* d_omega, const double* d_sigma,
                          double* d_G, void* stream, dyson_report* report);
 
+/* The same hot path at complex energies z_k with Im z_k > 0 instead of the
+ * Matsubara points i w_k: H_ii = z_k + mu - V_i - Sigma_i(z_k) (eq. (1)
+ * continued off the imaginary axis, e.g. z_k = w_k + i eta on the real
+ * axis).  d_z [K] complex; validation requires Im(z_k - Sigma_i) > 0.
+ * z_k = i w_k gives exactly the dyson_solve result for w_k. */
+dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const double* d_z,
+                           const double* d_sigma, double* d_G, void* stream,
+                           dyson_report* report);
+
 /* ---- Stage entry points (the same kernels the solve runs), for testing ----
  * All pointers are device pointers; the plan's workspace for K frequencies
  * is (re)allocated as needed. */
@@ -249,6 +259,10 @@ typedef struct dyson_req dyson_req;
 dyson_status dyson_serve_config(dyson_ctx* ctx, int slots, int max_batch_freqs);
 dyson_status dyson_submit(dyson_plan* plan, int K, const double* V, const double* omega,
                           const double* sigma, double* G, int mem, dyson_req** req);
+/* A request at complex energies z [K] complex (as dyson_solve_z); requests of
+ * both kinds on one plan share batches. */
+dyson_status dyson_submit_z(dyson_plan* plan, int K, const double* V, const double* z,
+                            const double* sigma, double* G, int mem, dyson_req** req);
 /* *done = 1 once the request has finished (successfully or not). */
 dyson_status dyson_poll(dyson_req* req, int* done);
 /* Block until the request finishes or timeout_s (< 0: no limit) passes.

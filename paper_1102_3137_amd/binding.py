@@ -87,12 +87,14 @@ SIGNATURES = [
     ("dyson_plan_get_maps", C.c_int, [_P, _I, _I, _I]),
     ("dyson_footprint", C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     ("dyson_solve", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_solve_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_assemble", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
     ("dyson_correct_level", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _I, _P]),
     ("dyson_serve_config", C.c_int, [_P, C.c_int, C.c_int]),
     ("dyson_submit", C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.c_int, C.POINTER(_P)]),
+    ("dyson_submit_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.c_int, C.POINTER(_P)]),
     ("dyson_poll", C.c_int, [_P, _I]),
     ("dyson_wait", C.c_int, [_P, C.c_double]),
     ("dyson_cancel", C.c_int, [_P]),
@@ -178,6 +180,11 @@ def dyson_solve(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream, report: Rep
                                       C.byref(report) if report is not None else None))
 
 
+def dyson_solve_z(plan, K, V_ptr, z_ptr, sigma_ptr, G_ptr, stream, report: Report | None = None):
+    _check(load_library().dyson_solve_z(plan, K, V_ptr, z_ptr, sigma_ptr, G_ptr, stream,
+                                        C.byref(report) if report is not None else None))
+
+
 def dyson_assemble(plan, K, V_ptr, omega_ptr, sigma_ptr, d_ptr, stream):
     _check(load_library().dyson_assemble(plan, K, V_ptr, omega_ptr, sigma_ptr, d_ptr, stream))
 
@@ -199,10 +206,10 @@ def dyson_serve_config(ctx, slots: int, max_batch_freqs: int):
     _check(load_library().dyson_serve_config(ctx, slots, max_batch_freqs))
 
 
-def dyson_submit(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem):
+def dyson_submit(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem, zmode=False):
     h = _P()
-    _check(load_library().dyson_submit(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem,
-                                       C.byref(h)))
+    fn = load_library().dyson_submit_z if zmode else load_library().dyson_submit
+    _check(fn(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, mem, C.byref(h)))
     return h
 
 
@@ -315,6 +322,18 @@ class Plan:
                     _ptr(self._c(G)), _stream(), rep)
         return (G, rep.as_dict()) if report else G
 
+    def solve_z(self, V, z, sigma, G=None, report=False):
+        """The solve at complex energies z (complex128 [K], Im z > 0)."""
+        import torch
+        K = int(z.shape[0])
+        assert z.is_cuda and z.dtype == torch.complex128 and z.is_contiguous()
+        if G is None:
+            G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
+        rep = Report()
+        dyson_solve_z(self.plan, K, _ptr(self._c(V)), _ptr(z), _ptr(self._c(sigma)),
+                      _ptr(self._c(G)), _stream(), rep)
+        return (G, rep.as_dict()) if report else G
+
     def assemble(self, V, omega, sigma):
         import torch
         K = int(omega.shape[0])
@@ -339,26 +358,29 @@ class Plan:
     def submit(self, V, omega, sigma, G=None, mem=MEM_DEVICE):
         """Queue a solve on the context's server.  mem=MEM_DEVICE: torch tensors on
         the GPU (complete when submitted); mem=MEM_HOST: numpy arrays (V float64 [N],
-        omega float64 [K], sigma complex128 [K, N]), G a complex128 [K, N] array."""
+        omega float64 [K], sigma complex128 [K, N]), G a complex128 [K, N] array.
+        A complex omega (complex128) is taken as the energies z_k (dyson_submit_z)."""
         import numpy as np
         K = int(omega.shape[0])
+        zmode = bool(omega.is_complex()) if hasattr(omega, "is_complex") else \
+            np.iscomplexobj(omega)
         if mem == MEM_DEVICE:
             import torch
             if G is None:
                 G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
             keep = (self._c(V), self._c(omega), self._c(sigma), self._c(G))
             h = dyson_submit(self.plan, K, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]),
-                             _ptr(keep[3]), MEM_DEVICE)
+                             _ptr(keep[3]), MEM_DEVICE, zmode)
         else:
             V = np.ascontiguousarray(V, np.float64)
-            omega = np.ascontiguousarray(omega, np.float64)
+            omega = np.ascontiguousarray(omega, np.complex128 if zmode else np.float64)
             sigma = np.ascontiguousarray(sigma, np.complex128)
             if G is None:
                 G = np.empty((K, self.n_sites), np.complex128)
             assert G.dtype == np.complex128 and G.flags.c_contiguous
             keep = (V, omega, sigma, G)
             cp = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
-            h = dyson_submit(self.plan, K, cp(V), cp(omega), cp(sigma), cp(G), MEM_HOST)
+            h = dyson_submit(self.plan, K, cp(V), cp(omega), cp(sigma), cp(G), MEM_HOST, zmode)
         return Request(h, G, keep)
 
     def correct_level(self, level, d, Gacc):

@@ -67,7 +67,7 @@ struct Work {
   int* d_count = nullptr;
   double* rho2 = nullptr;   // inner solves: r^T z of the last two iterations per item
   double* partS = nullptr;  // inner solves: per-unit p^T A p
-  double* stage_om = nullptr;  // [Kcap] staging of host-side frequencies
+  double* stage_om = nullptr;  // [2*Kcap] staging of host-side frequencies
   std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
   int* h_count = nullptr;   // pinned
   unsigned long long* d_prof = nullptr;
@@ -124,13 +124,15 @@ struct dyson_plan {
 namespace dyson {
 
 // One contiguous run of frequencies of a batch: K rows of the caller's (or a
-// staging) [K][N] arrays.  V is [N]; omega [K]; sigma and G [K][N] complex.
+// staging) [K][N] arrays.  V is [N]; omega [K] Matsubara w_k (zmode 0) or
+// [K] complex energies z_k (zmode 1); sigma and G [K][N] complex.
 struct Slice {
   int K;
   const double* V;
   const double* omega;
   const double* sigma;
   double* G;
+  int zmode;
 };
 
 // Correction levels per concurrent group: group 0 holds the level with the

@@ -79,12 +79,13 @@ struct LzArgs {
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
                     hipStream_t s);
 void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat, hipStream_t s);
+// omega: w_k [K] (zmode 0, z_k = i w_k) or complex z_k [K] (zmode 1)
 void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const double* omega,
-                     const double* sigma, double* d, hipStream_t s);
-// eq. (1) input checks, OR-ed into *flag: 1 non-finite V, 2 w_k <= 0 or
-// non-finite, 4 non-finite Sigma, 8 Im(i w_k - Sigma_i) <= 0.
-void launch_validate(int N, int K, const double* V, const double* omega, const double* sigma,
-                     int* flag, hipStream_t s);
+                     int zmode, const double* sigma, double* d, hipStream_t s);
+// eq. (1) input checks, OR-ed into *flag: 1 non-finite V, 2 Im z_k <= 0 or
+// non-finite z_k, 4 non-finite Sigma, 8 Im(z_k - Sigma_i) <= 0.
+void launch_validate(int N, int K, const double* V, const double* omega, int zmode,
+                     const double* sigma, int* flag, hipStream_t s);
 // Tile block factors of graph g (complex128 / complex64 / complex32 storage).
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s);
@@ -100,7 +101,7 @@ void launch_prof_collect(unsigned long long* per_item, int n, int classes, int f
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s);
 void launch_count_open(const int* done, int n, int* out, hipStream_t s);
 
-void launch_freq_keys(const double* omega, int K, uint64_t* fkey, hipStream_t s);
+void launch_freq_keys(const double* omega, int zmode, int K, uint64_t* fkey, hipStream_t s);
 void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s);
 void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s);
 void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,

@@ -33,9 +33,16 @@ __global__ void k_from_tile(TileGeom G, int K, const double* __restrict__ tile,
   st(nat, (size_t)k * G.N + i, ld(tile, (size_t)k * G.T * G.S + G.pos_of[i]));
 }
 
-// eq. (1): d_i(k) = i w_k + mu - V_i - Sigma_i(i w_k); padding sites get 1.
+// Frequency k's energy: z_k = i w_k (Matsubara, zmode 0: omega holds w_k)
+// or any z_k with Im z_k > 0 (zmode 1: omega holds complex z_k).
+__device__ __forceinline__ cd energy(const double* omega, int k, int zmode) {
+  return zmode ? ld(omega, k) : cmk(0.0, omega[k]);
+}
+
+// eq. (1): d_i(k) = z_k + mu - V_i - Sigma_i(z_k), z_k = i w_k on the
+// Matsubara axis; padding sites get 1.
 __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restrict__ V,
-                           const double* __restrict__ omega,
+                           const double* __restrict__ omega, int zmode,
                            const double* __restrict__ sigma, double* __restrict__ d) {
   const size_t NP = (size_t)G.T * G.S;
   size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,8 +51,8 @@ __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restric
   int i = G.site_of[p];
   cd v = cmk(1.0, 0.0);
   if (i >= 0) {
-    cd sg = ld(sigma, (size_t)k * G.N + i);
-    v = cmk(mu - V[i] - sg.x, omega[k] - sg.y);
+    const cd sg = ld(sigma, (size_t)k * G.N + i), z = energy(omega, k, zmode);
+    v = cmk(z.x + mu - V[i] - sg.x, z.y - sg.y);
   }
   st(d, (size_t)k * NP + p, v);
 }
@@ -53,17 +60,17 @@ __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restric
 // Input checks of eq. (1); Im(i w_k - Sigma_i) > 0 keeps Im H positive
 // definite, which the pivot-free factorizations rely on.
 __global__ void k_validate(int N, const double* __restrict__ V, const double* __restrict__ omega,
-                           const double* __restrict__ sigma, int* __restrict__ flag) {
+                           int zmode, const double* __restrict__ sigma, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (i >= N) return;
   int f = 0;
-  const double om = omega[k];
-  if (!isfinite(om) || !(om > 0.0)) f |= 2;
+  const cd z = energy(omega, k, zmode);
+  if (!isfinite(z.x) || !isfinite(z.y) || !(z.y > 0.0)) f |= 2;
   if (k == 0 && !isfinite(V[i])) f |= 1;
   const cd sg = ld(sigma, (size_t)k * N + i);
   if (!isfinite(sg.x) || !isfinite(sg.y)) f |= 4;
-  else if (!(om - sg.y > 0.0)) f |= 8;
+  else if (!(z.y - sg.y > 0.0)) f |= 8;
   if (f) atomicOr(flag, f);
 }
 
@@ -261,10 +268,21 @@ __global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict_
   if (tid == 0) st(a.partial, (size_t)k * G.T + t, qq);
 }
 
-__global__ void k_freq_keys(const double* __restrict__ omega, int K, uint64_t* __restrict__ fkey) {
+// Identity of frequency k for the start vectors: the bits of Im z_k, mixed
+// with those of Re z_k when it is not zero, so z_k = i w_k keys exactly as
+// the Matsubara frequency w_k.
+__global__ void k_freq_keys(const double* __restrict__ omega, int zmode, int K,
+                            uint64_t* __restrict__ fkey) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  fkey[k] = omega ? (uint64_t)__double_as_longlong(omega[k]) : (uint64_t)k;
+  if (!omega) {
+    fkey[k] = (uint64_t)k;
+    return;
+  }
+  const cd z = energy(omega, k, zmode);
+  uint64_t key = (uint64_t)__double_as_longlong(z.y);
+  if (z.x != 0.0) key ^= splitmix64((uint64_t)__double_as_longlong(z.x));
+  fkey[k] = key;
 }
 
 // q *= scal[item] (the inverse principal root of q^T q)
@@ -576,15 +594,15 @@ void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat,
   k_from_tile<<<grid, 256, 0, s>>>(G, K, tile, nat);
 }
 void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const double* omega,
-                     const double* sigma, double* d, hipStream_t s) {
+                     int zmode, const double* sigma, double* d, hipStream_t s) {
   size_t NP = (size_t)G.T * G.S;
   dim3 grid((unsigned)((NP + 255) / 256), K);
-  k_assemble<<<grid, 256, 0, s>>>(G, K, mu, V, omega, sigma, d);
+  k_assemble<<<grid, 256, 0, s>>>(G, K, mu, V, omega, zmode, sigma, d);
 }
-void launch_validate(int N, int K, const double* V, const double* omega, const double* sigma,
-                     int* flag, hipStream_t s) {
+void launch_validate(int N, int K, const double* V, const double* omega, int zmode,
+                     const double* sigma, int* flag, hipStream_t s) {
   dim3 grid((unsigned)((N + 255) / 256), K);
-  k_validate<<<grid, 256, 0, s>>>(N, V, omega, sigma, flag);
+  k_validate<<<grid, 256, 0, s>>>(N, V, omega, zmode, sigma, flag);
 }
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s) {
@@ -601,8 +619,8 @@ void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64
 void launch_count_open(const int* done, int n, int* out, hipStream_t s) {
   k_count_open<<<1, 256, 0, s>>>(done, n, out);
 }
-void launch_freq_keys(const double* omega, int K, uint64_t* fkey, hipStream_t s) {
-  k_freq_keys<<<(K + 63) / 64, 64, 0, s>>>(omega, K, fkey);
+void launch_freq_keys(const double* omega, int zmode, int K, uint64_t* fkey, hipStream_t s) {
+  k_freq_keys<<<(K + 63) / 64, 64, 0, s>>>(omega, zmode, K, fkey);
 }
 void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s) {
   k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, salt);

@@ -33,6 +33,7 @@ namespace dyson {
 struct ReqState {
   dyson_plan* plan = nullptr;
   int K = 0, mem = DYSON_MEM_DEVICE;
+  int zmode = 0;  // 0: omega holds Matsubara w_k; 1: complex energies z_k
   const double *V = nullptr, *omega = nullptr, *sigma = nullptr;  // device mode
   double* G = nullptr;                                             // caller's output
   std::vector<double> hV, hom, hsig;                               // host mode copies
@@ -214,10 +215,11 @@ struct Server {
     for (size_t j = 0; j < pieces.size(); ++j) {
       const Piece& pc = pieces[j];
       ReqState& r = *pc.r;
-      Slice s{pc.n, nullptr, nullptr, nullptr, nullptr};
+      const int zw = r.zmode ? 2 : 1;  // doubles per frequency
+      Slice s{pc.n, nullptr, nullptr, nullptr, nullptr, r.zmode};
       if (r.mem == DYSON_MEM_DEVICE) {
         s.V = r.V;
-        s.omega = r.omega + pc.k0;
+        s.omega = r.omega + (size_t)pc.k0 * zw;
         s.sigma = r.sigma + (size_t)pc.k0 * N * 2;
         s.G = r.G + (size_t)pc.k0 * N * 2;
       } else {
@@ -225,12 +227,12 @@ struct Server {
         // of xB that the batch's G will later be scattered to (xB is free
         // before the first correction level and after the last)
         double* sv = w->r + (size_t)j * N;
-        double* so = w->stage_om + k0;
+        double* so = w->stage_om + 2 * (size_t)k0;
         double* ss = w->xB + (size_t)k0 * NP * 2;
         if (hipMemcpyAsync(sv, r.hV.data(), (size_t)N * 8, hipMemcpyHostToDevice, sl.stream) !=
                 hipSuccess ||
-            hipMemcpyAsync(so, r.hom.data() + pc.k0, (size_t)pc.n * 8, hipMemcpyHostToDevice,
-                           sl.stream) != hipSuccess ||
+            hipMemcpyAsync(so, r.hom.data() + (size_t)pc.k0 * zw, (size_t)pc.n * zw * 8,
+                           hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
             hipMemcpyAsync(ss, r.hsig.data() + (size_t)pc.k0 * N * 2, (size_t)pc.n * N * 16,
                            hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
           set_error("host to device copy failed");
@@ -427,30 +429,32 @@ dyson_status start_server(dyson_ctx* c, std::shared_ptr<Server>* out) {
   return DYSON_OK;
 }
 
-dyson_status validate_host(int N, int K, const double* V, const double* om, const double* sg) {
+dyson_status validate_host(int N, int K, const double* V, const double* om, int zmode,
+                           const double* sg) {
   for (int i = 0; i < N; ++i)
     if (!std::isfinite(V[i])) return fail(DYSON_EINVAL, "V contains a non-finite value");
   for (int k = 0; k < K; ++k) {
-    if (!std::isfinite(om[k]) || !(om[k] > 0))
-      return fail(DYSON_EINVAL, "omega_k must be finite and > 0");
+    const double zr = zmode ? om[2 * k] : 0.0, zi = zmode ? om[2 * k + 1] : om[k];
+    if (!std::isfinite(zr) || !std::isfinite(zi) || !(zi > 0))
+      return fail(DYSON_EINVAL, "frequencies must be finite with w_k > 0 (Im z_k > 0)");
     for (int i = 0; i < N; ++i) {
       const double re = sg[2 * ((size_t)k * N + i)], im = sg[2 * ((size_t)k * N + i) + 1];
       if (!std::isfinite(re) || !std::isfinite(im))
         return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
-      if (!(om[k] - im > 0))
-        return fail(DYSON_EINVAL, "Im(i w_k - Sigma_i) must be > 0 (causal self-energy)");
+      if (!(zi - im > 0))
+        return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
     }
   }
   return DYSON_OK;
 }
 
 dyson_status validate_device(Server& srv, int N, int K, const double* V, const double* om,
-                             const double* sg) {
+                             int zmode, const double* sg) {
   std::lock_guard<std::mutex> g(srv.vm);
   if (hipSetDevice(srv.device) != hipSuccess ||
       hipMemsetAsync(srv.vflag, 0, sizeof(int), srv.vstream) != hipSuccess)
     return fail(DYSON_EDEVICE, "validation launch failed");
-  launch_validate(N, K, V, om, sg, srv.vflag, srv.vstream);
+  launch_validate(N, K, V, om, zmode, sg, srv.vflag, srv.vstream);
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(srv.hflag, srv.vflag, sizeof(int), hipMemcpyDeviceToHost, srv.vstream) !=
           hipSuccess ||
@@ -458,9 +462,59 @@ dyson_status validate_device(Server& srv, int N, int K, const double* V, const d
     return fail(DYSON_EDEVICE, "validation kernel failed");
   const int f = *srv.hflag;
   if (f & 1) return fail(DYSON_EINVAL, "V contains a non-finite value");
-  if (f & 2) return fail(DYSON_EINVAL, "omega_k must be finite and > 0");
+  if (f & 2) return fail(DYSON_EINVAL, "frequencies must be finite with w_k > 0 (Im z_k > 0)");
   if (f & 4) return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
-  if (f & 8) return fail(DYSON_EINVAL, "Im(i w_k - Sigma_i) must be > 0 (causal self-energy)");
+  if (f & 8) return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
+  return DYSON_OK;
+}
+
+}  // namespace
+
+namespace {
+
+dyson_status submit(dyson_plan* plan, int K, const double* V, const double* omega, int zmode,
+                    const double* sigma, double* G, int mem, dyson_req** req) {
+  if (!plan || !plan->ctx) return fail(DYSON_EINVAL, "plan has no device context");
+  if (!req) return fail(DYSON_EINVAL, "null request handle");
+  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  if (!V || !omega || !sigma || !G) return fail(DYSON_EINVAL, "null input or output pointer");
+  if (mem != DYSON_MEM_DEVICE && mem != DYSON_MEM_HOST) return fail(DYSON_EINVAL, "bad mem");
+  std::shared_ptr<Server> srv;
+  dyson_status s0 = start_server(plan->ctx, &srv);
+  if (s0 != DYSON_OK) return s0;
+  const int N = plan->hp.N;
+  auto r = std::make_shared<ReqState>();
+  r->plan = plan;
+  r->K = K;
+  r->mem = mem;
+  r->zmode = zmode;
+  r->G = G;
+  if (mem == DYSON_MEM_HOST) {
+    dyson_status sv = validate_host(N, K, V, omega, zmode, sigma);
+    if (sv != DYSON_OK) return sv;
+    r->hV.assign(V, V + N);
+    r->hom.assign(omega, omega + (size_t)K * (zmode ? 2 : 1));
+    r->hsig.assign(sigma, sigma + (size_t)2 * K * N);
+  } else {
+    dyson_status sv = validate_device(*srv, N, K, V, omega, zmode, sigma);
+    if (sv != DYSON_OK) return sv;
+    r->V = V;
+    r->omega = omega;
+    r->sigma = sigma;
+  }
+  r->t_arrive = Clock::now();
+  plan->live_requests.fetch_add(1);
+  {
+    std::lock_guard<std::mutex> g(srv->m);
+    if (srv->stop) {
+      plan->live_requests.fetch_sub(1);
+      return fail(DYSON_EINVAL, "the context is being destroyed");
+    }
+    srv->queue.push_back(r);
+    ++srv->gen;
+  }
+  srv->cv_work.notify_all();
+  *req = new dyson_req{srv, r};
   return DYSON_OK;
 }
 
@@ -482,47 +536,12 @@ dyson_status dyson_serve_config(dyson_ctx* ctx, int slots, int max_batch_freqs) 
 
 dyson_status dyson_submit(dyson_plan* plan, int K, const double* V, const double* omega,
                           const double* sigma, double* G, int mem, dyson_req** req) {
-  if (!plan || !plan->ctx) return fail(DYSON_EINVAL, "plan has no device context");
-  if (!req) return fail(DYSON_EINVAL, "null request handle");
-  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
-  if (!V || !omega || !sigma || !G) return fail(DYSON_EINVAL, "null input or output pointer");
-  if (mem != DYSON_MEM_DEVICE && mem != DYSON_MEM_HOST) return fail(DYSON_EINVAL, "bad mem");
-  std::shared_ptr<Server> srv;
-  dyson_status s0 = start_server(plan->ctx, &srv);
-  if (s0 != DYSON_OK) return s0;
-  const int N = plan->hp.N;
-  auto r = std::make_shared<ReqState>();
-  r->plan = plan;
-  r->K = K;
-  r->mem = mem;
-  r->G = G;
-  if (mem == DYSON_MEM_HOST) {
-    dyson_status sv = validate_host(N, K, V, omega, sigma);
-    if (sv != DYSON_OK) return sv;
-    r->hV.assign(V, V + N);
-    r->hom.assign(omega, omega + K);
-    r->hsig.assign(sigma, sigma + (size_t)2 * K * N);
-  } else {
-    dyson_status sv = validate_device(*srv, N, K, V, omega, sigma);
-    if (sv != DYSON_OK) return sv;
-    r->V = V;
-    r->omega = omega;
-    r->sigma = sigma;
-  }
-  r->t_arrive = Clock::now();
-  plan->live_requests.fetch_add(1);
-  {
-    std::lock_guard<std::mutex> g(srv->m);
-    if (srv->stop) {
-      plan->live_requests.fetch_sub(1);
-      return fail(DYSON_EINVAL, "the context is being destroyed");
-    }
-    srv->queue.push_back(r);
-    ++srv->gen;
-  }
-  srv->cv_work.notify_all();
-  *req = new dyson_req{srv, r};
-  return DYSON_OK;
+  return submit(plan, K, V, omega, 0, sigma, G, mem, req);
+}
+
+dyson_status dyson_submit_z(dyson_plan* plan, int K, const double* V, const double* z,
+                            const double* sigma, double* G, int mem, dyson_req** req) {
+  return submit(plan, K, V, z, 1, sigma, G, mem, req);
 }
 
 dyson_status dyson_poll(dyson_req* req, int* done) {

@@ -122,7 +122,7 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->lz_unorm2, ni * 8},  {(void**)&w->lz_umax2, ni * 8},
       {(void**)&w->lz_scal, ni * 16},   {(void**)&w->d_count, 16},
       {(void**)&w->d_prof, 64},         {(void**)&w->d_wprof, 4 * ni * 8},
-      {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 8},
+      {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 16},
       {(void**)&w->d_flag, 16}};
   if (sub) {
     std::vector<std::pair<void**, size_t>> keep;
@@ -565,7 +565,7 @@ dyson_status begin_call(dyson_plan* p, Work* w, int K, hipStream_t s) {
   w->stat_restarts = 0;
   w->stat_capped = 0;
   w->fac_g[0] = w->fac_g[1] = -1000;  // factors depend on d, which changes per call
-  launch_freq_keys(nullptr, K, w->d_fkey, s);
+  launch_freq_keys(nullptr, 0, K, w->d_fkey, s);
   return DYSON_OK;
 }
 
@@ -580,16 +580,16 @@ dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int 
     if (sl[j].K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
     if (!sl[j].V || !sl[j].omega || !sl[j].sigma || !sl[j].G)
       return fail(DYSON_EINVAL, "null input or output pointer");
-    launch_validate(N, sl[j].K, sl[j].V, sl[j].omega, sl[j].sigma, w->d_flag, s);
+    launch_validate(N, sl[j].K, sl[j].V, sl[j].omega, sl[j].zmode, sl[j].sigma, w->d_flag, s);
   }
   HIPC(hipGetLastError());
   HIPC(hipMemcpyAsync(w->h_count, w->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   const int f = w->h_count[0];
   if (f & 1) return fail(DYSON_EINVAL, "V contains a non-finite value");
-  if (f & 2) return fail(DYSON_EINVAL, "omega_k must be finite and > 0");
+  if (f & 2) return fail(DYSON_EINVAL, "frequencies must be finite with w_k > 0 (Im z_k > 0)");
   if (f & 4) return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
-  if (f & 8) return fail(DYSON_EINVAL, "Im(i w_k - Sigma_i) must be > 0 (causal self-energy)");
+  if (f & 8) return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
   return DYSON_OK;
 }
 
@@ -607,8 +607,8 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   const size_t NP = (size_t)P.T * P.S;
   // a1: diagonal of H, each slice into its rows of the batch
   for (int j = 0, k0 = 0; j < n; k0 += sl[j].K, ++j) {
-    launch_freq_keys(sl[j].omega, sl[j].K, w->d_fkey + k0, s);
-    launch_assemble(p->geom, sl[j].K, P.mu, sl[j].V, sl[j].omega, sl[j].sigma,
+    launch_freq_keys(sl[j].omega, sl[j].zmode, sl[j].K, w->d_fkey + k0, s);
+    launch_assemble(p->geom, sl[j].K, P.mu, sl[j].V, sl[j].omega, sl[j].zmode, sl[j].sigma,
                     w->d + (size_t)k0 * NP * 2, s);
   }
   // a3/a4: leaf factorization and diag(B^{-1})
@@ -900,7 +900,7 @@ dyson_status dyson_assemble(dyson_plan* p, int K, const double* d_V, const doubl
   hipStream_t s = (hipStream_t)stream;
   Work* w = p ? &p->main : nullptr;
   CHECKED(begin_call(p, w, K, s));
-  launch_assemble(p->geom, K, p->hp.mu, d_V, d_omega, d_sigma, w->d, s);
+  launch_assemble(p->geom, K, p->hp.mu, d_V, d_omega, 0, d_sigma, w->d, s);
   launch_from_tile(p->geom, K, w->d, d_d, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
@@ -967,7 +967,20 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
   Work* w = &p->main;
   HIPC(hipSetDevice(p->ctx->device));
   CHECKED(ensure_work(p, w, K, s));
-  Slice sl{K, d_V, d_omega, d_sigma, d_G};
+  Slice sl{K, d_V, d_omega, d_sigma, d_G, 0};
+  CHECKED(validate_slices(p, w, &sl, 1, s));
+  return run_solve(p, w, &sl, 1, s, rep, nullptr);
+}
+
+dyson_status dyson_solve_z(dyson_plan* p, int K, const double* d_V, const double* d_z,
+                           const double* d_sigma, double* d_G, void* stream, dyson_report* rep) {
+  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
+  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  Work* w = &p->main;
+  HIPC(hipSetDevice(p->ctx->device));
+  CHECKED(ensure_work(p, w, K, s));
+  Slice sl{K, d_V, d_z, d_sigma, d_G, 1};
   CHECKED(validate_slices(p, w, &sl, 1, s));
   return run_solve(p, w, &sl, 1, s, rep, nullptr);
 }

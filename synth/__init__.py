@@ -147,3 +147,16 @@ def serving_trace(n: int, rate: float, squares=(128, 256, 512), cubes=(32, 64),
             w = cubic(L, K, seed=1000 + rid, beta=beta)
         out.append((t, w))
     return out
+
+
+def real_axis_inputs(dims, K: int, eta: float = 0.1, w_range=(-3.0, 3.0), seed: int = 7,
+                     vc: float = 0.01, mu: float = 0.5):
+    """Inputs on the real-frequency axis: energies z_k = w_k + i eta on a
+    uniform grid of w_range, the trap V = vc r^2 and the per-site self-energy
+    model continued to z: Sigma_i(z) = a_i / (z + b_i) (Im Sigma <= 0).
+    Returns (V [N], z [K] complex, sigma [K, N] complex, mu)."""
+    n = int(np.prod(dims))
+    V = trap(dims, vc)
+    z = np.linspace(w_range[0], w_range[1], K) + 1j * eta
+    a, b = sigma_params(n, seed)
+    return V, z, a[None, :] / (z[:, None] + b[None, :]), mu

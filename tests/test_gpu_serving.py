@@ -190,3 +190,28 @@ def test_torch_allocator_hook():
     p.close()
     ctx.close()
     assert calls["alloc"] > 0 and calls["free"] == calls["alloc"]
+
+
+def test_real_axis_requests_share_batches():
+    """Requests at complex energies and at Matsubara frequencies on one plan
+    are batched together; each result equals its solo dyson_solve(_z)."""
+    ctx = Context(0, slots=1)
+    w = _w((40, 40), 3, 71)
+    p = _plan(ctx, w, 8)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    Vr, z, sigr, mu = synth.real_axis_inputs(w.dims, 3, mu=w.mu, vc=w.vc)
+    tVr = torch.from_numpy(Vr).cuda()
+    tz = torch.from_numpy(z).cuda()
+    tsr = torch.from_numpy(np.ascontiguousarray(sigr)).cuda()
+    alone_m = p.solve(tV, tom, tsig).cpu().numpy()
+    alone_z = p.solve_z(tVr, tz, tsr).cpu().numpy()
+    r1 = p.submit(tV, tom, tsig)
+    r2 = p.submit(tVr, tz, tsr)
+    r3 = p.submit(Vr, z, sigr, mem=MEM_HOST)
+    assert np.array_equal(r1.wait(timeout=120).cpu().numpy(), alone_m)
+    assert np.array_equal(r2.wait(timeout=120).cpu().numpy(), alone_z)
+    assert np.array_equal(r3.wait(timeout=120), alone_z)
+    for r in (r1, r2, r3):
+        r.release()
+    p.close()
+    ctx.close()
