@@ -201,6 +201,17 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
                            const double* d_sigma, double* d_G, void* stream,
                            dyson_report* report);
 
+/* Measured choice of the tile shape: for each candidate leaf edge (8, 12, 16
+ * on chains and squares; 4, 5, 6 on cubes; periodic axes keep only edges that
+ * divide them) and level-stream count (1, 4), a plan solves the probe inputs
+ * (K frequencies, device pointers as in dyson_solve) once after its
+ * workspace is allocated; the fastest wins.  *best = base (NULL: defaults)
+ * with leaf_edge and level_streams set; *rate = its site*freq/s.  The probe
+ * should be a few representative frequencies of the intended workload. */
+dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyson_opts* base,
+                            int K, const double* d_V, const double* d_omega,
+                            const double* d_sigma, dyson_opts* best, double* rate);
+
 /* ---- Stage entry points (the same kernels the solve runs), for testing ----
  * All pointers are device pointers; the plan's workspace for K frequencies
  * is (re)allocated as needed. */

@@ -92,6 +92,8 @@ SIGNATURES = [
     ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
     ("dyson_correct_level", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _I, _P]),
+    ("dyson_autotune", C.c_int, [_P, C.POINTER(Lattice), C.POINTER(Opts), C.c_int, _P, _P, _P,
+                                 C.POINTER(Opts), C.POINTER(C.c_double)]),
     ("dyson_serve_config", C.c_int, [_P, C.c_int, C.c_int]),
     ("dyson_submit", C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.c_int, C.POINTER(_P)]),
     ("dyson_submit_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, C.c_int, C.POINTER(_P)]),
@@ -403,6 +405,30 @@ class Context:
         self.handle = dyson_create(device, hbm_budget, allocator)
         if slots is not None or max_batch_freqs is not None:
             dyson_serve_config(self.handle, slots or 3, max_batch_freqs or 256)
+
+    def autotune(self, dims, V, omega, sigma, t=-1.0, mu=0.0, periodic=None, **opts):
+        """Measured leaf edge and level-stream count for this lattice on the
+        probe inputs (torch tensors on the GPU); returns a dict of options for
+        plan() and the probe's site*freq/s."""
+        lat = Lattice()
+        dims = tuple(int(x) for x in dims)
+        lat.dim = len(dims)
+        per = tuple(periodic) if periodic is not None else (0,) * len(dims)
+        for a in range(3):
+            lat.L[a] = dims[a] if a < len(dims) else 1
+            lat.periodic[a] = int(per[a]) if a < len(per) else 0
+        lat.t, lat.mu = float(t), float(mu)
+        base = Opts(0, opts.get("partition", PART_NESTED), opts.get("precision", PREC_FP64),
+                    opts.get("max_rank", 0), opts.get("extra_steps", 10),
+                    opts.get("max_inner_iters", 2000), opts.get("inner_tol", 1e-14),
+                    opts.get("lanczos_tol", 1e-11), opts.get("seed", 0x5EED), 0, 0)
+        best, rate = Opts(), C.c_double()
+        _check(load_library().dyson_autotune(self.handle, C.byref(lat), C.byref(base),
+                                             int(omega.shape[0]), _ptr(Plan._c(V)),
+                                             _ptr(Plan._c(omega)), _ptr(Plan._c(sigma)),
+                                             C.byref(best), C.byref(rate)))
+        return {"leaf_edge": best.leaf_edge, "level_streams": best.level_streams,
+                "rate": rate.value}
 
     def plan(self, dims, **kw) -> Plan:
         p = Plan(dims, ctx=self, **kw)

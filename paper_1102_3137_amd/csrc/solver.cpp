@@ -972,6 +972,58 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
   return run_solve(p, w, &sl, 1, s, rep, nullptr);
 }
 
+dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyson_opts* base,
+                            int K, const double* d_V, const double* d_omega,
+                            const double* d_sigma, dyson_opts* best, double* rate) {
+  if (!ctx || !lat || !best || K < 1) return fail(DYSON_EINVAL, "bad argument");
+  if (!d_V || !d_omega || !d_sigma) return fail(DYSON_EINVAL, "null input pointer");
+  const dyson_opts b0 = merge_opts(base);
+  std::vector<int> edges = (lat->dim == 3) ? std::vector<int>{4, 5, 6} : std::vector<int>{8, 12, 16};
+  const int streams[2] = {1, 4};
+  long long n = 1;
+  for (int a = 0; a < 3; ++a) n *= std::max(1, lat->L[a]);
+  HIPC(hipSetDevice(ctx->device));
+  double* G = (double*)dev_alloc(ctx, (size_t)K * n * 16, nullptr);
+  if (!G) return fail(DYSON_ENOMEM, "probe output allocation failed");
+  double best_s = -1.0;
+  dyson_status last = DYSON_EINVAL;
+  std::string last_err = "no valid candidate";
+  for (int e : edges)
+    for (int ls : streams) {
+      dyson_opts o = b0;
+      o.leaf_edge = e;
+      o.level_streams = ls;
+      o.profile = 0;
+      dyson_plan* p = nullptr;
+      if (dyson_plan_create(ctx, lat, &o, &p) != DYSON_OK) continue;  // e.g. periodic extent
+      Work* w = &p->main;
+      dyson_status st = ensure_work(p, w, K, nullptr);
+      Slice sl{K, d_V, d_omega, d_sigma, G, 0};
+      if (st == DYSON_OK) st = validate_slices(p, w, &sl, 1, nullptr);
+      if (st == DYSON_OK) {
+        (void)hipDeviceSynchronize();
+        auto t0 = std::chrono::steady_clock::now();
+        st = run_solve(p, w, &sl, 1, nullptr, nullptr, nullptr);
+        const double secs =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st == DYSON_OK && (best_s < 0 || secs < best_s)) {
+          best_s = secs;
+          *best = o;
+        }
+      }
+      if (st != DYSON_OK) {
+        last = st;
+        last_err = g_err;
+      }
+      dyson_plan_destroy(p);
+      if (st == DYSON_EINVAL) break;  // the probe inputs themselves are invalid
+    }
+  dev_free(ctx, G, nullptr);
+  if (best_s < 0) return fail(last, last_err);
+  if (rate) *rate = (double)n * K / best_s;
+  return DYSON_OK;
+}
+
 dyson_status dyson_solve_z(dyson_plan* p, int K, const double* d_V, const double* d_z,
                            const double* d_sigma, double* d_G, void* stream, dyson_report* rep) {
   if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");

@@ -215,3 +215,24 @@ def test_real_axis_requests_share_batches():
         r.release()
     p.close()
     ctx.close()
+
+
+def test_autotune_picks_a_valid_tile_shape():
+    """The measured choice is one of the candidates and the plan built with it
+    solves to the oracle's accuracy."""
+    ctx = Context(0)
+    w = _w((64, 48), 2, 81)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    best = ctx.autotune(w.dims, tV, tom, tsig, t=w.t, mu=w.mu, precision=PREC_MIXED16)
+    assert best["leaf_edge"] in (8, 12, 16) and best["level_streams"] in (1, 4)
+    assert best["rate"] > 0
+    p = ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=best["leaf_edge"], precision=PREC_MIXED16,
+                 level_streams=best["level_streams"])
+    G = p.solve(tV, tom, tsig).cpu().numpy()
+    assert oracle.rel_err(G, oracle_G(w, V, om, sig)) < 1e-10
+    # periodic axes keep only the edges that divide them
+    bp = ctx.autotune((48, 48), tV[:48 * 48].contiguous(), tom,
+                      tsig[:, :48 * 48].contiguous(), t=w.t, mu=w.mu, periodic=(1, 1))
+    assert bp["leaf_edge"] in (8, 12, 16) and 48 % bp["leaf_edge"] == 0
+    p.close()
+    ctx.close()

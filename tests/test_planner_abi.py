@@ -168,3 +168,11 @@ def test_periodic_plan_rejects_invalid(dims, s, per):
     with pytest.raises(B.DysonError) as e:
         _host_plan(dims, s, B.PART_NESTED, periodic=per)
     assert e.value.status == 1
+
+
+def test_autotune_rejects_bad_arguments():
+    lib = B.load_library()
+    lat = B.Lattice()
+    best = B.Opts()
+    assert lib.dyson_autotune(None, B.C.byref(lat), None, 1, None, None, None, B.C.byref(best),
+                              None) == B.EINVAL
