@@ -216,7 +216,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["mixed", "mixed16", "fp64"], default="mixed16")
-    ap.add_argument("--workload", choices=["square256", "square128", "small32"], default="square256")
+    ap.add_argument("--workload", choices=["square256", "square128", "small32", "cubic48"],
+                    default="square256")
+    ap.add_argument("--freqs", type=int, default=0,
+                    help="use only the first K frequencies of the workload (0 = all)")
     ap.add_argument("--inner-tol", type=float, default=1e-14,
                     help="relative residual of the inner solves")
     ap.add_argument("--lanczos-tol", type=float, default=1e-11)
@@ -264,10 +267,16 @@ def main():
 
     if args.workload == "square256":
         w, s, part = synth.SQUARE_256, 16, PART_NESTED
+    elif args.workload == "cubic48":
+        w, s, part = synth.CUBIC_48, 6, PART_NESTED
     elif args.workload == "square128":
         w, s, part = synth.scaled_square(128, 64), 16, PART_NESTED
     else:
         w, s, part = synth.SMALL_32, 16, PART_SINGLE
+    if args.freqs:
+        import dataclasses
+        w = dataclasses.replace(w, freq_index=w.freq_index[:args.freqs],
+                                name=f"{w.name.split(',')[0]}, K={min(args.freqs, w.n_freq)}")
     prec = {"mixed": PREC_MIXED, "mixed16": PREC_MIXED16, "fp64": PREC_FP64}[args.precision]
     dev = torch.device("cuda:0")
     V, om, sig = synth.make_inputs(w)
@@ -330,7 +339,24 @@ def main():
 
     # accuracy against the oracle on a sample of frequencies (outside the timed region)
     cpu, err, value = None, None, work / (ms_per_step / 1000.0)
-    if not args.no_cpu:
+    if not args.no_cpu and len(w.dims) == 3:
+        # a cubic lattice's exact diagonal is minutes per frequency on the host:
+        # check sampled sites of the lowest (hardest) frequency by sparse LU (O3)
+        import oracle
+        V0, om0, sig0 = synth.make_inputs(w)
+        d = oracle.assemble_diag(V0, om0[:1], sig0[:1], w.mu)
+        rng = np.random.default_rng(11)
+        sites = np.sort(rng.choice(w.n_sites, 12, replace=False))
+        Gh = G.cpu().numpy()
+        log(f"O3 check: sparse LU of frequency 0, {len(sites)} sites ...")
+        t0 = time.perf_counter()
+        ref = oracle.diag_inv_sampled(w.dims, d[0], w.t, sites)
+        err = float(np.max(np.abs(Gh[0, sites] - ref) / np.abs(ref)))
+        log(f"O3 check on {len(sites)} sites of frequency 0: {err:.3e} "
+            f"({time.perf_counter() - t0:.1f} s)")
+        if not err <= 1e-6:
+            value = 0.0
+    elif not args.no_cpu:
         cpu, ref = cpu_baseline(w, args.cpu_freqs)
         Gh = G.cpu().numpy()
         import oracle
@@ -368,8 +394,9 @@ def main():
         "dtype": {PREC_MIXED: "c64 preconditioner + f64", PREC_MIXED16: "c32 preconditioner + f64",
                   PREC_FP64: "f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": w.name + (", 16x16 subdomains, recursive bisection, full rank"
-                                         if part == PART_NESTED else ", 4 subdomains, full rank"),
+        "config": {"workload": w.name + (f", {s}^{len(w.dims)} subdomains, recursive bisection, "
+                                         "full rank" if part == PART_NESTED
+                                         else ", 4 subdomains, full rank"),
                    "lattice": list(w.dims), "n_freq": w.n_freq, "beta": w.beta,
                    "precision": args.precision, "inner_tol": args.inner_tol,
                    "lanczos_tol": args.lanczos_tol, "parallelism": "1 GPU"},
