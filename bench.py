@@ -220,6 +220,8 @@ def main():
                     default="square256")
     ap.add_argument("--freqs", type=int, default=0,
                     help="use only the first K frequencies of the workload (0 = all)")
+    ap.add_argument("--level-streams", type=int, default=4,
+                    help="concurrent correction-level groups (1 = bottom-up, least memory)")
     ap.add_argument("--inner-tol", type=float, default=1e-14,
                     help="relative residual of the inner solves")
     ap.add_argument("--lanczos-tol", type=float, default=1e-11)
@@ -286,7 +288,7 @@ def main():
     G = torch.empty((w.n_freq, w.n_sites), dtype=torch.complex128, device=dev)
     plan = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                 inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
-                profile=0 if args.no_profile else 1)
+                profile=0 if args.no_profile else 1, level_streams=args.level_streams)
     log(f"plan: {w.name}, levels={plan.info.levels}, "
         f"max m per level={[plan.info.max_m[l] for l in range(plan.info.levels)]}, "
         f"footprint={plan.footprint(w.n_freq) / 2**30:.2f} GiB")

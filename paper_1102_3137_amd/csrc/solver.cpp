@@ -506,10 +506,16 @@ struct Run {
       launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 0, 0, HP.opts.lanczos_tol, brk, s);
       launch_lz_scale(a, K, Qj(0), s);
       HIPC(hipGetLastError());
+      const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
       for (int j = 0; j < kmax; ++j) {
         int open = 0;
         CHECKED(count_open(w->lz_stopped, n_items, &open));
         if (open == 0) break;
+        if (verbose && j > 0 && j % 256 == 0) {
+          std::fprintf(stderr, "[dyson] level %d step %d: %d of %d items open\n", level, j, open,
+                       n_items);
+          std::fflush(stderr);
+        }
         const double* q = Qj(j);
         CHECKED(xmatvec(level, q, w->xH));
         launch_lz_alpha(a, K, q, w->xH, s);
