@@ -32,10 +32,11 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the device sources: counter-derived traffic is reported only
-    for the kernel version the counters were taken on."""
+    """Hash of the sources that define the dominant kernel (k_cocg_update):
+    counter-derived traffic is reported only for the kernel version the
+    counters were taken on."""
     h = hashlib.sha256()
-    for f in ["kernels.hip", "cocg.hip", "devcommon.h", "kernels.h"]:
+    for f in ["cocg.hip", "devcommon.h", "kernels.h"]:
         h.update(open(os.path.join(ROOT, "paper_1102_3137_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

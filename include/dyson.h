@@ -25,7 +25,8 @@
  *   - Errors are status codes; nothing throws across the ABI.  On error the
  *     output buffers are left untouched or partially written and must not
  *     be used; dyson_last_error() gives a message (thread-local).
- *   - Validation returns DYSON_EINVAL: dim not in {1,2,3}, any L < 1, K < 1,
+ *   - Validation returns DYSON_EINVAL: dim not in {1,2,3}, any L < 1, K < 1
+ *     or K > 65535 per call,
  *     w_k <= 0 (Im z_k <= 0), non-finite input, or Im(i w_k - Sigma_i) <= 0
  *     (Im(z_k - Sigma_i) <= 0); the last keeps Im H positive definite, so H
  *     and every principal submatrix are non-singular and the pivot-free

@@ -400,15 +400,15 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
 }
 
 // h[item][i] = sum over the domain's tiles of the partials (fixed order);
-// pass 0 also sums |r|^2 into h[item][nvec]
+// pass 0 also sums |r|^2 into h[item][nvec].  One block per item.
 __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
                              const int* __restrict__ thi, int nvec, int pass) {
-  const int item = blockIdx.y;
+  const int item = blockIdx.x;
   const int k = item / a.n_nodes, node = item % a.n_nodes;
   if (a.stopped[item]) return;
   if (pass == 1 && !a.reorth[item]) return;
   const int n = (pass == 0) ? nvec + 1 : nvec;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     cd s = cmk(0.0, 0.0);
     for (int t = tlo[node]; t < thi[node]; ++t)
       s = cadd(s, ld(a.hpart + ((size_t)k * a.G.T + t) * (size_t)a.hstride * 2, i));
@@ -645,8 +645,7 @@ void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int
 }
 void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec, int pass,
                        hipStream_t s) {
-  dim3 grid((nvec + 256) / 256, K * a.n_nodes);
-  k_cgs_reduce<<<grid, 256, 0, s>>>(a, K, tlo, thi, nvec, pass);
+  k_cgs_reduce<<<(unsigned)(K * a.n_nodes), 256, 0, s>>>(a, K, tlo, thi, nvec, pass);
 }
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
                        double* D, int pass, hipStream_t s) {

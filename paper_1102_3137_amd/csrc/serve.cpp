@@ -454,7 +454,12 @@ dyson_status validate_device(Server& srv, int N, int K, const double* V, const d
   if (hipSetDevice(srv.device) != hipSuccess ||
       hipMemsetAsync(srv.vflag, 0, sizeof(int), srv.vstream) != hipSuccess)
     return fail(DYSON_EDEVICE, "validation launch failed");
-  launch_validate(N, K, V, om, zmode, sg, srv.vflag, srv.vstream);
+  // frequencies index the second grid dimension: at most 65535 per launch
+  for (int k0 = 0; k0 < K; k0 += 65535) {
+    const int kn = std::min(K - k0, 65535);
+    launch_validate(N, kn, V, om + (size_t)k0 * (zmode ? 2 : 1), zmode,
+                    sg + (size_t)k0 * N * 2, srv.vflag, srv.vstream);
+  }
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(srv.hflag, srv.vflag, sizeof(int), hipMemcpyDeviceToHost, srv.vstream) !=
           hipSuccess ||

@@ -80,6 +80,10 @@ Prof::~Prof() {
 
 namespace {
 
+// Frequencies of one batch: they index the second grid dimension of the
+// per-(tile, frequency) launches.
+constexpr int kMaxFreqs = 65535;
+
 // Lanczos step cap of a domain with interface size m: the paper allows 5-10
 // steps beyond m for m ~ 100; bilinear Lanczos in floating point needs more
 // as m grows (m + 11 observed at m = 128), so the allowance scales as m/8.
@@ -562,7 +566,7 @@ struct Run {
 // Clears the per-call statistics and the factor cache of a Work.
 dyson_status begin_call(dyson_plan* p, Work* w, int K, hipStream_t s) {
   if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
-  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  if (K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "K must be in [1, 65535]");
   HIPC(hipSetDevice(p->ctx->device));
   CHECKED(ensure_work(p, w, K, s));
   w->pending = DYSON_OK;
@@ -968,7 +972,7 @@ dyson_status dyson_correct_level(dyson_plan* p, int level, int K, const double* 
 dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* d_omega,
                          const double* d_sigma, double* d_G, void* stream, dyson_report* rep) {
   if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
-  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  if (K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "K must be in [1, 65535]");
   hipStream_t s = (hipStream_t)stream;
   Work* w = &p->main;
   HIPC(hipSetDevice(p->ctx->device));
@@ -981,7 +985,7 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
 dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyson_opts* base,
                             int K, const double* d_V, const double* d_omega,
                             const double* d_sigma, dyson_opts* best, double* rate) {
-  if (!ctx || !lat || !best || K < 1) return fail(DYSON_EINVAL, "bad argument");
+  if (!ctx || !lat || !best || K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "bad argument");
   if (!d_V || !d_omega || !d_sigma) return fail(DYSON_EINVAL, "null input pointer");
   const dyson_opts b0 = merge_opts(base);
   std::vector<int> edges = (lat->dim == 3) ? std::vector<int>{4, 5, 6} : std::vector<int>{8, 12, 16};
@@ -1033,7 +1037,7 @@ dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyso
 dyson_status dyson_solve_z(dyson_plan* p, int K, const double* d_V, const double* d_z,
                            const double* d_sigma, double* d_G, void* stream, dyson_report* rep) {
   if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
-  if (K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
+  if (K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "K must be in [1, 65535]");
   hipStream_t s = (hipStream_t)stream;
   Work* w = &p->main;
   HIPC(hipSetDevice(p->ctx->device));

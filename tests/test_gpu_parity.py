@@ -221,6 +221,10 @@ def test_invalid_inputs_rejected():
     with pytest.raises(DysonError) as e:
         p.solve(tV, tom, sig2)
     assert e.value.status == 1
+    # more frequencies in one call than the launch grid holds: refused up front
+    from paper_1102_3137_amd import binding as B
+    assert B.load_library().dyson_solve(p.plan, 70000, None, None, None, None, None,
+                                        None) == 1
 
 
 @pytest.mark.parametrize("L,freqs,prec", [(128, (0, 1, 31, 63), 1), (128, (0, 63), 0),

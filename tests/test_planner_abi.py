@@ -176,3 +176,13 @@ def test_autotune_rejects_bad_arguments():
     best = B.Opts()
     assert lib.dyson_autotune(None, B.C.byref(lat), None, 1, None, None, None, B.C.byref(best),
                               None) == B.EINVAL
+
+
+def test_solve_rejects_too_many_frequencies_per_call():
+    """K indexes the second grid dimension of the per-(tile, frequency)
+    launches; a call beyond 65535 frequencies is refused before any launch."""
+    lib = B.load_library()
+    plan = _host_plan((16, 16), 8, B.PART_NESTED)
+    # the plan has no device context: the argument checks still run first
+    assert lib.dyson_solve(plan, 70000, None, None, None, None, None, None) == B.EINVAL
+    B.dyson_plan_destroy(plan)
