@@ -236,3 +236,32 @@ def test_autotune_picks_a_valid_tile_shape():
     assert bp["leaf_edge"] in (8, 12, 16) and 48 % bp["leaf_edge"] == 0
     p.close()
     ctx.close()
+
+
+def test_many_requests_split_and_merged_across_batches():
+    """Twenty requests on three plans with a batch cap of 5 frequencies: a
+    request's frequencies spread over several batches and batches mix
+    requests.  Every result equals its solo solve bit for bit."""
+    ctx = Context(0, slots=3, max_batch_freqs=5)
+    shapes = [((32, 40), 8), ((48, 32), 16), ((10, 10, 10), 5)]
+    plans = [_plan(ctx, _w(d, 1, 0), s) for d, s in shapes]
+    rng = np.random.default_rng(5)
+    jobs = []
+    for rid in range(20):
+        pi = int(rng.integers(3))
+        w = _w(shapes[pi][0], int(rng.integers(1, 8)), 300 + rid, beta=float(rng.uniform(5, 30)))
+        V, om, sig, tV, tom, tsig = device_inputs(w)
+        jobs.append((pi, tV, tom, tsig))
+    alone = [plans[pi].solve(tV, tom, tsig).cpu().numpy() for pi, tV, tom, tsig in jobs]
+    torch.cuda.synchronize()
+    reqs = [plans[pi].submit(tV, tom, tsig) for pi, tV, tom, tsig in jobs]
+    multi = 0
+    for i, r in enumerate(reqs):
+        G = r.wait(timeout=300).cpu().numpy()
+        multi += r.report()["batches"] > 1
+        assert np.array_equal(G, alone[i]), f"request {i}"
+        r.release()
+    assert multi > 0  # some request did span batches
+    for p in plans:
+        p.close()
+    ctx.close()
