@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the hot kernels with HIP events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
-    ap.add_argument("--cpu-freqs", type=int, default=8)
+    ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--plain-baseline", action="store_true",
                     help="also time the plain per-frequency FP64 solve on 4 sampled frequencies")
     ap.add_argument("--calibrate-copy", action="store_true",
