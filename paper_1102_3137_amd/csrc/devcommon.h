@@ -124,6 +124,12 @@ __device__ __forceinline__ double u01(uint64_t z) {  // [0,1)
 }
 
 
+// v / s for the tile edge s and 0 <= v < 2^16: one multiply-high by the
+// precomputed floor(2^32/s) + 1 (exact: the rounding error stays below 1/s)
+__device__ __forceinline__ int div_edge(const TileGeom& G, int v) {
+  return (int)__umulhi((unsigned)v, G.edge_magic);
+}
+
 // Neighbour of tile-local site l in direction dir (0..5 = -x,+x,-y,+y,-z,+z):
 // the same tile or the adjacent one; false at the lattice edge.
 __device__ __forceinline__ bool site_nbr(const TileGeom& G, int t, int l, int dir, int& nt,
@@ -131,7 +137,8 @@ __device__ __forceinline__ bool site_nbr(const TileGeom& G, int t, int l, int di
   const int s = G.edge, a = dir >> 1, up = dir & 1;
   if (a >= G.dim) return false;
   const int stride = (a == 0) ? 1 : (a == 1 ? s : s * s);
-  const int c = (l / stride) % s;
+  const int q1 = div_edge(G, l), q2 = div_edge(G, q1);
+  const int c = (a == 0) ? l - s * q1 : (a == 1 ? q1 - s * q2 : q2);
   if (up ? (c < s - 1) : (c > 0)) {
     nt = t;
     nl = up ? l + stride : l - stride;

@@ -17,6 +17,7 @@ struct TileGeom {
   const int* pos_of;     // [N]
   int edge;              // tile edge s (tile = s^dim sites)
   int dim;               // lattice dimension 1..3
+  unsigned edge_magic;   // floor(2^32 / s) + 1: v / s = mulhi(v, edge_magic) for v < 2^16
 };
 
 // Per-item scalars of the inner COCG solves (item = k * n_nodes + node).

@@ -838,7 +838,8 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
       p->lv.push_back(d);
     }
     p->geom = TileGeom{P.T, P.S, P.sx, P.sy, P.N, P.t, p->d_nbr, p->d_kind, p->d_depth,
-                       p->d_site_of, p->d_pos_of, P.s, P.dim};
+                       p->d_site_of, p->d_pos_of, P.s, P.dim,
+                       (unsigned)(0x100000000ULL / (unsigned)P.s) + 1u};
   }
   *out = p.release();
   return DYSON_OK;
