@@ -207,6 +207,7 @@ def serve_bench(args):
         "speedup_vs_sequential": t_seq / t_serve,
         "mismatches_vs_alone": mismatch,
         "max_rel_err_sampled": err,
+        "est_rel_err_device": max(r["est_rel_err"] for r in reports),
     }
     print(json.dumps(out), flush=True)
 
@@ -406,6 +407,7 @@ def main():
         "latency_s": {"p50": lat_sorted[len(lat) // 2],
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "max_rel_err_sampled": err,
+        "est_rel_err_device": max(r["est_rel_err"] for r in reports),
         "plain_fp64_per_frequency": plain,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -100,6 +100,12 @@ typedef struct {
                          1 = one after the other, bottom-up.  Results do not
                          depend on timing; the group sums are added in a fixed
                          order [4] */
+  int check_sites;    /* sampled error estimate (report.est_rel_err): at this
+                         many fixed sites (0..2; the first on the top-level
+                         interface, the second inside a subdomain) the exact
+                         G_ii = e_i^T H^{-1} e_i is also computed by solving
+                         H x = e_i directly (eq. (14)) with the inner solver,
+                         for every frequency; -1 = none [2] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */
@@ -126,6 +132,10 @@ typedef struct {
   int batches;              /* device batches the request's frequencies ran in */
   size_t hbm_bytes;         /* largest workspace (device bytes) of those batches,
                                or of the call for dyson_solve */
+  double est_rel_err;       /* largest relative difference, over the check sites
+                               and frequencies, between G_ii and the direct solve
+                               of H x = e_i (opts.check_sites); 0 when no check
+                               ran (no correction level, or check_sites = -1) */
 } dyson_report;
 
 typedef struct dyson_ctx dyson_ctx;

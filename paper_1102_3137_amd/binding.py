@@ -38,7 +38,7 @@ class Opts(C.Structure):
     _fields_ = [("leaf_edge", C.c_int), ("partition", C.c_int), ("precision", C.c_int),
                 ("max_rank", C.c_int), ("extra_steps", C.c_int), ("max_inner_iters", C.c_int),
                 ("inner_tol", C.c_double), ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
-                ("profile", C.c_int), ("level_streams", C.c_int)]
+                ("profile", C.c_int), ("level_streams", C.c_int), ("check_sites", C.c_int)]
 
 
 class Report(C.Structure):
@@ -47,7 +47,7 @@ class Report(C.Structure):
                 ("inner_iters_max", C.c_int), ("restarts", C.c_int), ("truncated", C.c_int),
                 ("kern_ms", C.c_double * 4), ("kern_launches", C.c_longlong * 4),
                 ("kern_bytes", C.c_double * 4), ("t_queue_ms", C.c_double),
-                ("batches", C.c_int), ("hbm_bytes", C.c_size_t)]
+                ("batches", C.c_int), ("hbm_bytes", C.c_size_t), ("est_rel_err", C.c_double)]
 
     def as_dict(self):
         return {"t_total_ms": self.t_total_ms, "levels": self.levels,
@@ -56,7 +56,8 @@ class Report(C.Structure):
                 "restarts": self.restarts, "truncated": self.truncated,
                 "kern_ms": list(self.kern_ms), "kern_launches": list(self.kern_launches),
                 "kern_bytes": list(self.kern_bytes), "t_queue_ms": self.t_queue_ms,
-                "batches": self.batches, "hbm_bytes": int(self.hbm_bytes)}
+                "batches": self.batches, "hbm_bytes": int(self.hbm_bytes),
+                "est_rel_err": self.est_rel_err}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -257,7 +258,8 @@ class Plan:
     def __init__(self, dims, t=-1.0, mu=0.0, leaf_edge=16, partition=PART_NESTED,
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
                  inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
-                 ctx: "Context | None" = None, level_streams=4, periodic=None):
+                 ctx: "Context | None" = None, level_streams=4, periodic=None,
+                 check_sites=2):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
@@ -267,7 +269,8 @@ class Plan:
             lat.periodic[a] = int(per[a]) if a < len(per) else 0
         lat.t, lat.mu = float(t), float(mu)
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
-                 inner_tol, lanczos_tol, seed, int(profile), int(level_streams))
+                 inner_tol, lanczos_tol, seed, int(profile), int(level_streams),
+                 int(check_sites) if check_sites else -1)
         self.dims = dims
         self.n_sites = 1
         for x in dims:

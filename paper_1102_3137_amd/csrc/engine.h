@@ -75,6 +75,7 @@ struct Work {
                                           // inner solves in [0,2), Lanczos in [2,4)
   uint64_t* d_fkey = nullptr;
   int* d_flag = nullptr;    // input validation flags
+  double* d_err = nullptr;  // sampled error estimate
   Prof prof;
   // run statistics of the current call
   long long stat_inner = 0;
@@ -117,6 +118,7 @@ struct dyson_plan {
   int kcap = 1;     // largest Lanczos step cap + 1 (basis vectors)
   int nmax = 1;     // most domains on one level
   int hstride = 1;
+  std::vector<int> check_pos;  // tile positions of the sampled error check
   dyson::Work main;  // workspace of the blocking entry points
   std::atomic<int> live_requests{0};
 };

@@ -126,5 +126,9 @@ void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, c
                        int op, int j, double tol, double brk, hipStream_t s);
 void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s);
 void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s);
+// Sampled check: b = e_pos in every frequency row; err = max(err, max_k |x - g| / |x|) at pos.
+void launch_unit_vector(const TileGeom& G, int K, int pos, double* b, hipStream_t s);
+void launch_sample_err(const TileGeom& G, int K, int pos, const double* x, const double* g,
+                       double* err, hipStream_t s);
 
 }  // namespace dyson

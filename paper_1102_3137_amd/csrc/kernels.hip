@@ -569,6 +569,29 @@ __global__ void k_lz_reopen(LzArgs a, int n_items) {
   a.stopped[item] = (a.stopped[item] == 3) ? 0 : 4;
 }
 
+// b = e_pos in every frequency row (tile layout)
+__global__ void k_unit_vector(TileGeom G, int pos, double* __restrict__ b) {
+  const size_t NP = (size_t)G.T * G.S;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (p >= NP) return;
+  st(b, (size_t)k * NP + p, cmk(p == (size_t)pos ? 1.0 : 0.0, 0.0));
+}
+
+// err = max(err, max_k |x_k - g_k| / |x_k|) at tile position pos; one thread
+__global__ void k_sample_err(TileGeom G, int K, int pos, const double* __restrict__ x,
+                             const double* __restrict__ g, double* __restrict__ err) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const size_t NP = (size_t)G.T * G.S;
+  double e = err[0];
+  for (int k = 0; k < K; ++k) {
+    const cd xv = ld(x, (size_t)k * NP + pos), gv = ld(g, (size_t)k * NP + pos);
+    const double r = sqrt(cabs2(csub(xv, gv)) / cabs2(xv));
+    e = (r > e || r != r) ? r : e;
+  }
+  err[0] = e;
+}
+
 // G += D over the level's domains
 __global__ void k_add_into(LzArgs a, const double* __restrict__ D, double* __restrict__ G) {
   const int t = blockIdx.x, k = blockIdx.y;
@@ -671,6 +694,14 @@ void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s) {
   k_lz_clear_bad<<<tiles_grid(a.G, K), 256, 0, s>>>(a, D);
   const int n = K * a.n_nodes;
   k_lz_reopen<<<(n + 127) / 128, 128, 0, s>>>(a, n);
+}
+void launch_unit_vector(const TileGeom& G, int K, int pos, double* b, hipStream_t s) {
+  const size_t NP = (size_t)G.T * G.S;
+  k_unit_vector<<<dim3((unsigned)((NP + 255) / 256), K), 256, 0, s>>>(G, pos, b);
+}
+void launch_sample_err(const TileGeom& G, int K, int pos, const double* x, const double* g,
+                       double* err, hipStream_t s) {
+  k_sample_err<<<1, 64, 0, s>>>(G, K, pos, x, g, err);
 }
 void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s) {
   k_add_into<<<tiles_grid(a.G, K), 256, 0, s>>>(a, D, G);

@@ -24,6 +24,7 @@ dyson_opts default_opts() {
   o.seed = 0x5eedULL;
   o.profile = 0;
   o.level_streams = 4;
+  o.check_sites = 2;
   return o;
 }
 
@@ -41,6 +42,7 @@ dyson_opts merge_opts(const dyson_opts* u) {
   if (u->seed) o.seed = u->seed;
   o.profile = u->profile;
   if (u->level_streams) o.level_streams = u->level_streams;
+  if (u->check_sites) o.check_sites = u->check_sites < 0 ? 0 : u->check_sites;
   return o;
 }
 
@@ -72,6 +74,7 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
     return "unknown precision";
   if (opts.max_rank < 0 || opts.extra_steps < 0) return "max_rank and extra_steps must be >= 0";
   if (opts.level_streams < 1 || opts.level_streams > 8) return "level_streams must be in [1, 8]";
+  if (opts.check_sites < 0 || opts.check_sites > 2) return "check_sites must be in [-1, 2]";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
   if (n > (1LL << 28)) return "lattice too large";
 

@@ -312,6 +312,11 @@ struct Server {
         a.restarts += rep.restarts;
         a.truncated |= rep.truncated;
         a.hbm_bytes = std::max(a.hbm_bytes, sl.work.bytes);
+        // the batch's check covers every frequency in it, this request's too
+        if (st == DYSON_OK)
+          a.est_rel_err = (rep.est_rel_err != rep.est_rel_err || a.est_rel_err != a.est_rel_err)
+                              ? std::nan("")
+                              : std::max(a.est_rel_err, rep.est_rel_err);
         for (int c = 0; c < 4; ++c) {
           a.kern_ms[c] += rep.kern_ms[c];
           a.kern_launches[c] += rep.kern_launches[c];

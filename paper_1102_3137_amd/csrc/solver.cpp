@@ -127,12 +127,13 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->lz_scal, ni * 16},   {(void**)&w->d_count, 16},
       {(void**)&w->d_prof, 64},         {(void**)&w->d_wprof, 4 * ni * 8},
       {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 16},
-      {(void**)&w->d_flag, 16}};
+      {(void**)&w->d_flag, 16},        {(void**)&w->d_err, 16}};
   if (sub) {
     std::vector<std::pair<void**, size_t>> keep;
     for (auto& e : t)
       if (e.first != (void**)&w->d && e.first != (void**)&w->d_fkey &&
-          e.first != (void**)&w->stage_om && e.first != (void**)&w->d_flag)
+          e.first != (void**)&w->stage_om && e.first != (void**)&w->d_flag &&
+          e.first != (void**)&w->d_err)
         keep.push_back(e);
     return keep;
   }
@@ -364,7 +365,8 @@ struct Run {
   // COCG on graph g for every item of `level`, x = A_g^{-1} b.  Two launches
   // per iteration; the host polls the device's open-item count only near the
   // iteration count the previous solve of the same kind needed.
-  dyson_status cocg(int level, int g, const void* fac, const double* b, double* x) {
+  dyson_status cocg(int level, int g, const void* fac, const double* b, double* x,
+                    bool skip_stopped = true) {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
     CocgLaunch c{};
@@ -373,7 +375,7 @@ struct Run {
     c.g = g;
     c.tile_node = L.tile_node;
     c.n_nodes = L.n;
-    c.item_skip = w->lz_stopped;
+    c.item_skip = skip_stopped ? w->lz_stopped : nullptr;
     c.st = w->cst;
     c.d = w->d;
     c.x = x;
@@ -706,6 +708,27 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
     for (int g = 1; g < G; ++g) launch_add_into(all, K, w->sub[g - 1]->gacc, w->gacc, s);
     HIPC(hipGetLastError());
   }
+  // sampled error estimate: G_ii against e_i^T H^{-1} e_i from a direct
+  // inner solve of H x = e_i (eq. (14)) at the check sites, every frequency
+  double est = 0.0;
+  const int nchk = std::min<int>(P.opts.check_sites, (int)p->check_pos.size());
+  if (nchk > 0) {
+    const dyson_status saved = w->pending;
+    w->pending = DYSON_OK;
+    HIPC(hipMemsetAsync(w->d_err, 0, sizeof(double), s));
+    void* fac0 = nullptr;
+    CHECKED(run.factors_for(0, 0, &fac0));
+    for (int c = 0; c < nchk; ++c) {
+      launch_unit_vector(p->geom, K, p->check_pos[c], w->rhs, s);
+      CHECKED(run.cocg(0, 0, fac0, w->rhs, w->xH, false));
+      launch_sample_err(p->geom, K, p->check_pos[c], w->xH, w->gacc, w->d_err, s);
+    }
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(&est, w->d_err, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (w->pending != DYSON_OK) est = std::nan("");  // the check itself did not converge
+    w->pending = saved;
+  }
   int max_rank_used = 0;
   long long lsteps = 0;
   for (auto& v : lsteps_of)
@@ -733,6 +756,7 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
     rep->truncated = w->stat_capped > 0 ? 1 : 0;
     rep->batches = 1;
     rep->hbm_bytes = w->bytes;
+    rep->est_rel_err = est;
     if (w->prof.on) {
       for (int g = 0; g < G; ++g) {
         Work* gw = (g == 0) ? w : w->sub[g - 1].get();
@@ -840,6 +864,21 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
     p->geom = TileGeom{P.T, P.S, P.sx, P.sy, P.N, P.t, p->d_nbr, p->d_kind, p->d_depth,
                        p->d_site_of, p->d_pos_of, P.s, P.dim,
                        (unsigned)(0x100000000ULL / (unsigned)P.s) + 1u};
+    // check sites: a top-level interface site and a subdomain site, both
+    // found from the middle of the lattice in natural order
+    if (!P.levels.empty()) {
+      auto find = [&](int from, auto pred) {
+        for (int q = 0; q < P.N; ++q) {
+          const int i = (from + q) % P.N;
+          if (pred(P.pos_of[i])) return P.pos_of[i];
+        }
+        return -1;
+      };
+      const int a = find(P.N / 2, [&](int pos) { return P.kind[pos] == KIND_SEP && P.depth[pos] == 0; });
+      const int b = find((P.N / 2 + P.N / 3) % P.N, [&](int pos) { return P.kind[pos] == KIND_LEAF; });
+      if (a >= 0) p->check_pos.push_back(a);
+      if (b >= 0) p->check_pos.push_back(b);
+    }
   }
   *out = p.release();
   return DYSON_OK;

@@ -351,3 +351,18 @@ def test_real_axis_vs_oracle(dims, s, prec):
     print(f"real axis {dims} s={s} prec={prec} err={err:.2e} rep={rep}")
     assert rep["truncated"] == 0
     assert err < 1e-10
+
+
+def test_sampled_error_estimate_tracks_accuracy():
+    """report.est_rel_err (G_ii against a direct solve of H x = e_i at two
+    sites) is at the method's accuracy for a full-rank solve and exposes a
+    truncated rank."""
+    w = _case((48, 40), K=3)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    G, rep = _plan(w, 8, 0, 2).solve(tV, tom, tsig, report=True)
+    err = oracle.rel_err(G.cpu().numpy(), oracle_G(w, V, om, sig))
+    assert 0 < rep["est_rel_err"] < 1e-9 and err < 1e-10
+    _, rep_t = _plan(w, 8, 0, 2, max_rank=8).solve(tV, tom, tsig, report=True)
+    assert rep_t["truncated"] == 1 and rep_t["est_rel_err"] > 1e-4
+    _, rep_n = _plan(w, 8, 0, 2, check_sites=0).solve(tV, tom, tsig, report=True)
+    assert rep_n["est_rel_err"] == 0.0
