@@ -164,9 +164,10 @@ typedef struct {
 /* Context on one HIP device.  device = ordinal.  hbm_budget = device bytes
  * the serving slots may hold at once (0 = 90% of the device memory free at
  * creation); blocking calls allocate outside it.  allocator = NULL uses
- * hipMalloc/hipFree.  dyson_destroy stops the server: frequencies still
- * queued are dropped (their requests end with DYSON_ECANCELLED), batches on
- * the device finish first.  Request handles stay valid until released. */
+ * hipMalloc/hipFree.  Teardown order: release requests, destroy plans, then
+ * the context; dyson_destroy returns DYSON_EBUSY while plans made on it
+ * exist (and a plan refuses destruction while it has requests), so no work
+ * is in flight when the server stops. */
 dyson_status dyson_create(dyson_ctx** ctx, int device, size_t hbm_budget,
                           const dyson_allocator* allocator);
 dyson_status dyson_destroy(dyson_ctx* ctx);

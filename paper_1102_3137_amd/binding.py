@@ -386,7 +386,7 @@ class Plan:
             keep = (V, omega, sigma, G)
             cp = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
             h = dyson_submit(self.plan, K, cp(V), cp(omega), cp(sigma), cp(G), MEM_HOST, zmode)
-        return Request(h, G, keep)
+        return Request(h, G, keep, self)
 
     def correct_level(self, level, d, Gacc):
         import numpy as np
@@ -454,10 +454,11 @@ class Context:
 
 
 class Request:
-    """Handle of a submitted solve; G is filled when it finishes successfully."""
+    """Handle of a submitted solve; G is filled when it finishes successfully.
+    It keeps its plan (and the arrays it borrows) alive until released."""
 
-    def __init__(self, handle, G, keep):
-        self.handle, self.G, self._keep = handle, G, keep
+    def __init__(self, handle, G, keep, plan=None):
+        self.handle, self.G, self._keep, self._plan = handle, G, keep, plan
 
     def done(self) -> bool:
         return dyson_poll(self.handle)
@@ -482,6 +483,7 @@ class Request:
             dyson_release(self.handle)
             self.handle = None
             self._keep = None
+            self._plan = None
 
     def __del__(self):
         try:

@@ -102,6 +102,7 @@ struct dyson_ctx {
   std::shared_ptr<dyson::Server> server;  // started by the first dyson_submit
   int slots = 3;
   int max_batch_freqs = 256;
+  std::atomic<int> live_plans{0};
   ~dyson_ctx();  // stops the server (serve.cpp)
 };
 

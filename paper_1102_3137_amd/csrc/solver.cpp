@@ -813,6 +813,9 @@ dyson_status dyson_create(dyson_ctx** ctx, int device, size_t hbm_budget,
 }
 
 dyson_status dyson_destroy(dyson_ctx* ctx) {
+  if (!ctx) return DYSON_OK;
+  if (ctx->live_plans.load() > 0)
+    return fail(DYSON_EBUSY, "context has plans that are not yet destroyed");
   delete ctx;  // stops the server first (serve.cpp)
   return DYSON_OK;
 }
@@ -861,6 +864,7 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
       HIPC(hipMemcpy(d.mcap, cap.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
       p->lv.push_back(d);
     }
+    ctx->live_plans.fetch_add(1);
     p->geom = TileGeom{P.T, P.S, P.sx, P.sy, P.N, P.t, p->d_nbr, p->d_kind, p->d_depth,
                        p->d_site_of, p->d_pos_of, P.s, P.dim,
                        (unsigned)(0x100000000ULL / (unsigned)P.s) + 1u};
@@ -903,6 +907,7 @@ dyson_status dyson_plan_destroy(dyson_plan* p) {
     (void)hipFree(p->d_depth);
     (void)hipFree(p->d_site_of);
     (void)hipFree(p->d_pos_of);
+    p->ctx->live_plans.fetch_sub(1);
   }
   delete p;
   return DYSON_OK;

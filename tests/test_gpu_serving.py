@@ -265,3 +265,40 @@ def test_many_requests_split_and_merged_across_batches():
     for p in plans:
         p.close()
     ctx.close()
+
+
+def test_cancel_a_request_sharing_a_batch():
+    """Two requests on one plan share a batch; cancelling one leaves the other
+    complete and exact, and the cancelled one ends with DYSON_ECANCELLED."""
+    ctx = Context(0, slots=1)
+    w = _w((96, 96), 6, 91, beta=20.0)
+    p = _plan(ctx, w, 16)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    ref = p.solve(tV, tom, tsig).cpu().numpy()
+    ra = p.submit(tV, tom, tsig)
+    rb = p.submit(tV, tom, tsig)
+    rb.cancel()
+    assert rb.status(timeout=300) == B.ECANCELLED
+    assert np.array_equal(ra.wait(timeout=300).cpu().numpy(), ref)
+    ra.release()
+    rb.release()
+    # teardown order is enforced: the context refuses while a plan exists
+    with pytest.raises(DysonError) as e:
+        B.dyson_destroy(ctx.handle)
+    assert e.value.status == B.EBUSY
+    p.close()
+    ctx.close()
+
+
+def test_fp64_requests_match_solo():
+    ctx = Context(0, slots=2)
+    w = _w((40, 48), 3, 101)
+    p = _plan(ctx, w, 8, prec=PREC_FP64)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    ref = p.solve(tV, tom, tsig).cpu().numpy()
+    r = p.submit(V, om, sig, mem=MEM_HOST)
+    G = r.wait(timeout=120)
+    assert np.array_equal(G, ref) and r.report()["est_rel_err"] < 1e-9
+    r.release()
+    p.close()
+    ctx.close()
