@@ -219,6 +219,17 @@ __device__ __forceinline__ void tile_solve_any(const WaveFactor<F, REG>& f, cons
   wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
 }
 
+// Item state: 0 open; 1 closed at the start (zero right-hand side or a
+// stopped Lanczos item); otherwise the mark of the launch that closed it.  A
+// unit that reads its own launch's mark was closed by a sibling unit of the
+// same item during this launch: it still applies its tile's share of the
+// closing work (the pending x update), as the sibling did.
+__device__ __forceinline__ int stencil_mark(int it) { return 4 * it + 3; }
+__device__ __forceinline__ int update_mark(int it) { return 4 * it + 4; }
+__device__ __forceinline__ bool open_here(int state, int mark) {
+  return state == 0 || state == mark;
+}
+
 // ------------------------------------------------------------- kernels
 // r = b (masked to graph g), x = 0, p = 0, z = M^{-1} r;
 // item totals: rho = r^T z, bn2 = |b|^2
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
 // p_new = z + beta p_old ; s = A_g p_new ; partial mu = p^T s
 __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   const Unit u = decode(a);
-  if (!u.ok || a.st.done[u.item]) return;
+  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)u.k * NP;
@@ -305,9 +316,17 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   if (it > 0) {
     cd rho, rr;
     item_sum(a.partU, 2, a, u, rho, rr);
-    if (rr.x <= a.tol2 * a.st.bn2[u.item]) {
+    if (a.flush || rr.x <= a.tol2 * a.st.bn2[u.item]) {
+      if (it & 1) {  // the last update was even: x still lacks alpha_{i-1} p_{i-1}
+        const cd ap = ld(a.alph, u.item);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int l = u.lane + 64 * e;
+          if (l < G.S && ac[e]) st(a.x, base + l, cfma(ap, po[e], ld(a.x, base + l)));
+        }
+      }
       if (lead && u.lane == 0) {
-        a.st.done[u.item] = 1;
+        a.st.done[u.item] = stencil_mark(it);
         a.st.iters[u.item] = it;
       }
       return;
@@ -363,12 +382,16 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   if (u.lane == 0) st(a.partS, (size_t)u.k * G.T + u.t, mu);
 }
 
-// x += alpha p ; r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z,
-// |r|^2 ; converged when |r|^2 <= tol^2 |b|^2, else beta = rho'/rho
+// r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z, |r|^2 ; converged
+// when |r|^2 <= tol^2 |b|^2, else beta = rho'/rho.  x += alpha p is applied
+// every other iteration: on odd iterations x += alpha_{i-1} p_{i-1} + alpha_i
+// p_i (both directions are still resident), on even ones alpha_i is kept for
+// the next; the stencil launch that finds an item converged after an even
+// iteration applies the pending alpha_{i-1} p_{i-1}.
 template <typename F, bool REG>
 __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   const Unit u = decode(a);
-  if (!u.ok || a.st.done[u.item]) return;
+  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   const F* fac = (const F*)a.fac;
@@ -378,14 +401,29 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
-    if (u.t == a.tlo[u.node] && u.lane == 0) a.st.done[u.item] = 2;
+    if (it & 1) {  // apply the pending alpha_{i-1} p_{i-1} before closing the item
+      const cd ap = ld(a.alph, u.item);
+      for (int l = u.lane; l < G.S; l += 64) {
+        const size_t p = (size_t)u.t * G.S + l;
+        if (active(G.kind[p], G.depth[p], a.g))
+          st(a.x, base + l, cfma(ap, ld(a.p_old, base + l), ld(a.x, base + l)));
+      }
+    }
+    if (u.t == a.tlo[u.node] && u.lane == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
   const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
-  if (a.wctr && u.t == a.tlo[u.node] && u.lane == 0)
-    a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-                      ((unsigned long long)(G.S * (7 * 16 + 2)) +
-                       (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  const bool odd = it & 1;
+  if (u.t == a.tlo[u.node] && u.lane == 0) {
+    if (!odd) st(a.alph, u.item, alpha);
+    // algorithmic bytes: r, s read and r, z written every iteration; x read and
+    // written and p_{i-1}, p_i read on odd ones; the factors
+    if (a.wctr)
+      a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+                        ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
+                         (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  }
+  const cd aprev = odd ? ld(a.alph, u.item) : cmk(0.0, 0.0);
   __shared__ cd zsh[WAVES][256];
   __shared__ cd rsh[WAVES][256];
   __shared__ uint8_t ash[WAVES][256];
@@ -402,8 +440,9 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
       const size_t p = (size_t)u.t * G.S + l;
       ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
       if (ac) {
-        const cd pv = ld(a.p_new, base + l);
-        st(a.x, base + l, cfma(alpha, pv, ld(a.x, base + l)));
+        if (odd)
+          st(a.x, base + l,
+             cfma(alpha, ld(a.p_new, base + l), cfma(aprev, ld(a.p_old, base + l), ld(a.x, base + l))));
         rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
       }
       st(a.r, base + l, rv);
@@ -624,7 +663,7 @@ __global__ __launch_bounds__(256) void k_cocg_init_planes(CocgLaunch a,
 // afterwards, so the loads do not wait on the flags.
 __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
   const Unit u = decode_wg(a);
-  if (!u.ok || a.st.done[u.item]) return;
+  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)u.k * NP;
@@ -634,9 +673,15 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
   if (it > 0) {
     cd rho, rr;
     item_sum(a.partU, 2, a, u, rho, rr);
-    if (rr.x <= a.tol2 * a.st.bn2[u.item]) {
+    if (a.flush || rr.x <= a.tol2 * a.st.bn2[u.item]) {
+      const int l = threadIdx.x;
+      if ((it & 1) && l < G.S) {  // pending alpha_{i-1} p_{i-1} of the deferred x update
+        const size_t p = (size_t)u.t * G.S + l;
+        if (active(G.kind[p], G.depth[p], a.g))
+          st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
+      }
       if (lead && threadIdx.x == 0) {
-        a.st.done[u.item] = 1;
+        a.st.done[u.item] = stencil_mark(it);
         a.st.iters[u.item] = it;
       }
       return;
@@ -690,20 +735,31 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
 template <typename F>
 __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it) {
   const Unit u = decode_wg(a);
-  if (!u.ok || a.st.done[u.item]) return;
+  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if (cabs2(mu) == 0.0) {
-    if (u.t == a.tlo[u.node] && threadIdx.x == 0) a.st.done[u.item] = 2;
+    const int l = threadIdx.x;
+    if ((it & 1) && l < G.S) {
+      const size_t p = (size_t)u.t * G.S + l;
+      if (active(G.kind[p], G.depth[p], a.g))
+        st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
+    }
+    if (u.t == a.tlo[u.node] && threadIdx.x == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
   const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
-  if (a.wctr && u.t == a.tlo[u.node] && threadIdx.x == 0)
-    a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-                      ((unsigned long long)(G.S * (7 * 16 + 2)) +
-                       (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  const bool odd = it & 1;
+  if (u.t == a.tlo[u.node] && threadIdx.x == 0) {
+    if (!odd) st(a.alph, u.item, alpha);
+    if (a.wctr)
+      a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
+                        ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
+                         (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+  }
+  const cd aprev = odd ? ld(a.alph, u.item) : cmk(0.0, 0.0);
   __shared__ cd zl[256];
   __shared__ uint8_t act[256];
   const F* fac = (const F*)a.fac;
@@ -717,8 +773,9 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
     const size_t p = (size_t)u.t * G.S + l;
     ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
     if (ac) {
-      const cd pv = ld(a.p_new, base + l);
-      st(a.x, base + l, cfma(alpha, pv, ld(a.x, base + l)));
+      if (odd)
+        st(a.x, base + l,
+           cfma(alpha, ld(a.p_new, base + l), cfma(aprev, ld(a.p_old, base + l), ld(a.x, base + l))));
       rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
     }
     st(a.r, base + l, rv);
@@ -766,11 +823,12 @@ __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* _
       st(a.rho2, item, s0);
       a.st.iters[item] = 0;
       a.st.done[item] = (s1.x > 0.0) ? 0 : 1;
-    } else if (s1.x <= a.tol2 * a.st.bn2[item]) {
-      a.st.done[item] = 1;
-      a.st.iters[item] = it;
+      mine += a.st.done[item] == 0;
+    } else {
+      // converged items are marked (and their deferred x update applied) by
+      // the next stencil launch; here they only stop counting as open
+      mine += !(s1.x <= a.tol2 * a.st.bn2[item]);
     }
-    mine += a.st.done[item] == 0;
   }
   atomicAdd(&cnt, mine);
   __syncthreads();

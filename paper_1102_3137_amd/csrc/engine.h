@@ -66,6 +66,7 @@ struct Work {
          *lz_scal = nullptr;
   int* d_count = nullptr;
   double* rho2 = nullptr;   // inner solves: r^T z of the last two iterations per item
+  double* alph = nullptr;   // inner solves: alpha of the last even iteration per item
   double* partS = nullptr;  // inner solves: per-unit p^T A p
   double* stage_om = nullptr;  // [2*Kcap] staging of host-side frequencies
   std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling

@@ -48,7 +48,10 @@ struct CocgLaunch {
   double* partS;         // [K*T] complex: p^T A p per unit
   double* partU;         // [K*T*2] complex: r^T z and |r|^2 per unit
   double* rho2;          // [2][n_items] complex: r^T z of the last two iterations
+  double* alph;          // [n_items] complex: alpha of the last even iteration (x is
+                         // updated every other iteration, alpha_{i-1} p_{i-1} + alpha_i p_i)
   double tol2;           // squared relative residual target
+  int flush;             // final stencil launch: close every open item
 };
 
 struct LzArgs {

@@ -119,6 +119,7 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->h, ni * p->hstride * 16},
       {(void**)&w->cst.done, ni * 4},  {(void**)&w->cst.iters, ni * 4},
       {(void**)&w->cst.bn2, ni * 8},   {(void**)&w->rho2, ni * 32},
+      {(void**)&w->alph, ni * 16},
       {(void**)&w->partS, (size_t)K * P.T * 16},
       {(void**)&w->lz_stopped, ni * 4}, {(void**)&w->lz_steps, ni * 4},
       {(void**)&w->lz_reorth, ni * 4},
@@ -394,6 +395,7 @@ struct Run {
     c.partS = w->partS;
     c.partU = w->partial;
     c.rho2 = w->rho2;
+    c.alph = w->alph;
     c.tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
     const int slot = 2 * level + (g == level ? 0 : 1);
     if ((int)w->pred.size() <= slot) w->pred.resize(slot + 1, 0);
@@ -416,6 +418,10 @@ struct Run {
         check_at = it + (it < 8 ? 1 : 2);
       }
     }
+    // closes the items still open: applies the x update deferred from an even
+    // last iteration (also to items stopped by max_inner_iters)
+    c.flush = 1;
+    if (it > 0) launch_cocg_stencil(c, it, s);
     HIPC(hipGetLastError());
     if (open != 0) {
       w->pending = DYSON_ENOCONV;
