@@ -22,6 +22,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The solve runs its correction-level groups (and the server its requests) on
+# separate HIP streams.  HIP maps streams onto 4 hardware queues by default,
+# and streams that share a queue run one after another; 16 queues give each
+# stream its own.  Read when the HIP runtime starts, so set before torch loads.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 KERNEL_NAMES = ["k_cocg_update", "k_cocg_stencil", "k_cgs_update", "k_cgs_dot"]
@@ -229,6 +234,9 @@ def main():
     ap.add_argument("--lanczos-tol", type=float, default=1e-11)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the hot kernels with HIP events")
+    ap.add_argument("--no-standalone", action="store_true",
+                    help="skip the untimed solve that times the dominant kernel with the "
+                         "levels in sequence")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--plain-baseline", action="store_true",
@@ -340,6 +348,25 @@ def main():
                 "hot_path_algorithmic_bytes_per_step": round(all_b),
                 "hot_path_GBps_over_step": round(path_gbs, 1),
                 "hot_path_frac": round(path_gbs / PEAK_HBM_GBS, 4)}
+        if args.level_streams > 1 and not args.no_standalone:
+            # the same kernel with nothing beside it: one untimed solve with the
+            # levels run one after another, so each launch has the GPU alone
+            ps = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
+                      inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=1,
+                      level_streams=1)
+            t0 = time.perf_counter()
+            _, r1 = ps.solve(tV, tom, tsig, G, report=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter() - t0
+            ps.close()
+            ms1, nb1, nl1 = r1["kern_ms"][c], r1["kern_bytes"][c], r1["kern_launches"][c]
+            a1 = nb1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
+            roof["standalone"] = {"level_streams": 1, "achieved": round(a1, 1),
+                                  "frac": round(a1 / PEAK_HBM_GBS, 4),
+                                  "avg_launch_us": round(1000.0 * ms1 / max(nl1, 1), 2),
+                                  "launches": nl1, "solve_s": round(t1, 3)}
+            log(f"standalone {KERNEL_NAMES[c]}: {a1:.1f} GB/s over {nl1} launches "
+                f"(levels in sequence, {t1:.2f} s)")
 
     # accuracy against the oracle on a sample of frequencies (outside the timed region)
     cpu, err, value = None, None, work / (ms_per_step / 1000.0)

@@ -374,6 +374,9 @@ class Plan:
             if G is None:
                 G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
             keep = (self._c(V), self._c(omega), self._c(sigma), self._c(G))
+            # the server reads the inputs on its own streams: they must be
+            # complete when the request is queued
+            torch.cuda.current_stream(V.device).synchronize()
             h = dyson_submit(self.plan, K, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]),
                              _ptr(keep[3]), MEM_DEVICE, zmode)
         else:

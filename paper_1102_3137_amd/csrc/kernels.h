@@ -22,7 +22,7 @@ struct TileGeom {
 
 // Per-item scalars of the inner COCG solves (item = k * n_nodes + node).
 struct CocgState {
-  int* done;       // 0 open, 1 converged/skipped, 2 bilinear breakdown
+  int* done;       // 0 open, 1 closed at the start, else the mark of the closing launch
   int* iters;
   double* bn2;     // |b|^2
 };
