@@ -81,20 +81,24 @@ __global__ void k_validate(int N, const double* __restrict__ V, const double* __
 // the bonds between slices y-1 and y.  The dense inverses S_y^{-1} (n x n,
 // complex symmetric, pivot-free because Im > 0) are stored per slice,
 // symmetrized so that lower-precision copies stay exactly symmetric.
-constexpr int NMAX = 36;  // widest slice: a 6 x 6 plane
-
+// NM = widest slice the instance handles (16: rows of square tiles and planes
+// of 4^3 tiles; 36: planes of 5^3 and 6^3 tiles).  256 threads per block; each
+// owns PER entries of the slice matrix, kept in registers across a pivot step.
+template <int NM>
 struct FactorSmem {
+  static constexpr int PER = (NM * NM + 255) / 256;
   cd dl[256];
   uint8_t act[256];
-  cd A[NMAX][NMAX + 1];
-  cd Gp[NMAX][NMAX + 1];
-  cd tmp[NMAX][NMAX + 1];
+  cd A[NM][NM + 1];
+  cd Gp[NM][NM + 1];
+  cd tmp[NM][NM + 1];
 };
 
-__device__ __forceinline__ void factor_load(FactorSmem& sm, const TileGeom& G, int g, int t, int k,
-                                            const double* __restrict__ d) {
+template <int NM>
+__device__ __forceinline__ void factor_load(FactorSmem<NM>& sm, const TileGeom& G, int g, int t,
+                                            int k, const double* __restrict__ d) {
   const size_t NP = (size_t)G.T * G.S;
-  for (int l = threadIdx.x; l < G.S; l += blockDim.x) {
+  for (int l = threadIdx.x; l < G.S; l += 256) {
     const size_t p = (size_t)t * G.S + l;
     sm.dl[l] = ld(d, (size_t)k * NP + p);
     sm.act[l] = active(G.kind[p], G.depth[p], g) ? 1 : 0;
@@ -103,10 +107,15 @@ __device__ __forceinline__ void factor_load(FactorSmem& sm, const TileGeom& G, i
 }
 
 // Forms S_y (into A) and inverts it in place (Gauss-Jordan, no pivoting).
-__device__ __forceinline__ void factor_slice(FactorSmem& sm, const TileGeom& G, int y) {
+template <int NM>
+__device__ __forceinline__ void factor_slice(FactorSmem<NM>& sm, const TileGeom& G, int y) {
+  constexpr int PER = FactorSmem<NM>::PER;
   const int n = G.sx, nn = n * n;
   const double tt = G.t;
-  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int e = threadIdx.x + 256 * c;
+    if (e >= nn) break;
     const int i = e / n, j = e % n;
     const int li = i + n * y, lj = j + n * y;
     const bool ai = sm.act[li], aj = sm.act[lj];
@@ -119,35 +128,42 @@ __device__ __forceinline__ void factor_slice(FactorSmem& sm, const TileGeom& G, 
   }
   __syncthreads();
   for (int q = 0; q < n; ++q) {
-    cd nv[6];
-    int c = 0;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) {
-      const int i = e / n, j = e % n;
-      const cd pinv = cdiv(cmk(1.0, 0.0), sm.A[q][q]);
-      if (i == q && j == q) nv[c] = pinv;
-      else if (i == q) nv[c] = cmul(sm.A[q][j], pinv);
-      else if (j == q) nv[c] = cscale(cmul(sm.A[i][q], pinv), -1.0);
-      else nv[c] = csub(sm.A[i][j], cmul(cmul(sm.A[i][q], sm.A[q][j]), pinv));
+    const cd pinv = cdiv(cmk(1.0, 0.0), sm.A[q][q]);
+    cd nv[PER];
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      nv[c] = cmk(0.0, 0.0);
+      if (e < nn) {
+        const int i = e / n, j = e % n;
+        if (i == q && j == q) nv[c] = pinv;
+        else if (i == q) nv[c] = cmul(sm.A[q][j], pinv);
+        else if (j == q) nv[c] = cscale(cmul(sm.A[i][q], pinv), -1.0);
+        else nv[c] = csub(sm.A[i][j], cmul(cmul(sm.A[i][q], sm.A[q][j]), pinv));
+      }
     }
     __syncthreads();
-    c = 0;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) sm.A[e / n][e % n] = nv[c];
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (e < nn) sm.A[e / n][e % n] = nv[c];
+    }
     __syncthreads();
   }
 }
 
-template <typename F>
+template <typename F, int NM>
 __global__ __launch_bounds__(256) void k_factor(TileGeom G, int g, const int* __restrict__ tile_node,
                                                 const double* __restrict__ d, F* __restrict__ fac) {
   const int t = blockIdx.x, k = blockIdx.y;
   if (tile_node && tile_node[t] < 0) return;
-  __shared__ FactorSmem sm;
+  __shared__ FactorSmem<NM> sm;
   factor_load(sm, G, g, t, k, d);
   const int n = G.sx, nn = n * n;
   const size_t fbase = ((size_t)k * G.T + t) * (size_t)G.sy * nn;
   for (int y = 0; y < G.sy; ++y) {
     factor_slice(sm, G, y);
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    for (int e = threadIdx.x; e < nn; e += 256) {
       const int i = e / n, j = e % n;
       stf<F>(fac, fbase + (size_t)y * nn + e, cscale(cadd(sm.A[i][j], sm.A[j][i]), 0.5));
       sm.Gp[i][j] = sm.A[i][j];
@@ -159,11 +175,13 @@ __global__ __launch_bounds__(256) void k_factor(TileGeom G, int g, const int* __
 // Leaf graph (every separator inactive): factors in complex128 and the exact
 // diagonal of each leaf block's inverse (eq. (13), first term) by the backward
 // recursion G_yy = S_y^{-1} + S_y^{-1} T_{y+1} G_{y+1,y+1} T_{y+1} S_y^{-1}.
+template <int NM>
 __global__ __launch_bounds__(256) void k_factor_diag(TileGeom G, const double* __restrict__ d,
                                                      double* __restrict__ fac,
                                                      double* __restrict__ gdiag) {
+  constexpr int PER = FactorSmem<NM>::PER;
   const int t = blockIdx.x, k = blockIdx.y;
-  __shared__ FactorSmem sm;
+  __shared__ FactorSmem<NM> sm;
   factor_load(sm, G, 255, t, k, d);
   const int n = G.sx, nn = n * n, ns = G.sy;
   const double tt = G.t;
@@ -171,7 +189,7 @@ __global__ __launch_bounds__(256) void k_factor_diag(TileGeom G, const double* _
   const size_t fbase = ((size_t)k * G.T + t) * (size_t)ns * nn;
   for (int y = 0; y < ns; ++y) {
     factor_slice(sm, G, y);
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    for (int e = threadIdx.x; e < nn; e += 256) {
       const int i = e / n, j = e % n;
       st(fac, fbase + (size_t)y * nn + e, cscale(cadd(sm.A[i][j], sm.A[j][i]), 0.5));
       sm.Gp[i][j] = sm.A[i][j];
@@ -180,18 +198,18 @@ __global__ __launch_bounds__(256) void k_factor_diag(TileGeom G, const double* _
   }
   // Gp = G_{ns-1,ns-1}
   auto write_diag = [&](int y) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += 256) {
       const size_t p = (size_t)t * G.S + i + n * y;
       if (G.kind[p] == 1) st(gdiag, (size_t)k * NP + p, sm.Gp[i][i]);
     }
   };
   write_diag(ns - 1);
   for (int y = ns - 2; y >= 0; --y) {
-    for (int e = threadIdx.x; e < nn; e += blockDim.x)
+    for (int e = threadIdx.x; e < nn; e += 256)
       sm.A[e / n][e % n] = ld(fac, fbase + (size_t)y * nn + e);  // S_y^{-1}
     __syncthreads();
     // tmp = C M C S_y^{-1}, C = diag(bonds between slices y and y+1)
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    for (int e = threadIdx.x; e < nn; e += 256) {
       const int i = e / n, j = e % n;
       cd acc = cmk(0.0, 0.0);
       if (sm.act[i + n * (y + 1)] && sm.act[i + n * y])
@@ -200,17 +218,24 @@ __global__ __launch_bounds__(256) void k_factor_diag(TileGeom G, const double* _
       sm.tmp[i][j] = acc;
     }
     __syncthreads();
-    cd nv[6];
-    int c = 0;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) {
-      const int i = e / n, j = e % n;
-      cd acc = cmk(0.0, 0.0);
-      for (int l = 0; l < n; ++l) acc = cfma(sm.A[i][l], sm.tmp[l][j], acc);
-      nv[c] = cadd(sm.A[i][j], cscale(acc, tt * tt));
+    cd nv[PER];
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      nv[c] = cmk(0.0, 0.0);
+      if (e < nn) {
+        const int i = e / n, j = e % n;
+        cd acc = cmk(0.0, 0.0);
+        for (int l = 0; l < n; ++l) acc = cfma(sm.A[i][l], sm.tmp[l][j], acc);
+        nv[c] = cadd(sm.A[i][j], cscale(acc, tt * tt));
+      }
     }
     __syncthreads();
-    c = 0;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x, ++c) sm.Gp[e / n][e % n] = nv[c];
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (e < nn) sm.Gp[e / n][e % n] = nv[c];
+    }
     __syncthreads();
     write_diag(y);
     __syncthreads();
@@ -630,13 +655,20 @@ void launch_validate(int N, int K, const double* V, const double* omega, int zmo
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s) {
   dim3 grid = tiles_grid(G, K);
-  if (fp16) k_factor<__half><<<grid, 256, 0, s>>>(G, g, tile_node, d, (__half*)fac);
-  else if (fp32) k_factor<float><<<grid, 256, 0, s>>>(G, g, tile_node, d, (float*)fac);
-  else k_factor<double><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac);
+  if (G.sx <= 16) {
+    if (fp16) k_factor<__half, 16><<<grid, 256, 0, s>>>(G, g, tile_node, d, (__half*)fac);
+    else if (fp32) k_factor<float, 16><<<grid, 256, 0, s>>>(G, g, tile_node, d, (float*)fac);
+    else k_factor<double, 16><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac);
+  } else {
+    if (fp16) k_factor<__half, 36><<<grid, 256, 0, s>>>(G, g, tile_node, d, (__half*)fac);
+    else if (fp32) k_factor<float, 36><<<grid, 256, 0, s>>>(G, g, tile_node, d, (float*)fac);
+    else k_factor<double, 36><<<grid, 256, 0, s>>>(G, g, tile_node, d, (double*)fac);
+  }
 }
 void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64, double* gdiag,
                         hipStream_t s) {
-  k_factor_diag<<<tiles_grid(G, K), 256, 0, s>>>(G, d, fac64, gdiag);
+  if (G.sx <= 16) k_factor_diag<16><<<tiles_grid(G, K), 256, 0, s>>>(G, d, fac64, gdiag);
+  else k_factor_diag<36><<<tiles_grid(G, K), 256, 0, s>>>(G, d, fac64, gdiag);
 }
 
 void launch_count_open(const int* done, int n, int* out, hipStream_t s) {
