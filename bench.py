@@ -84,14 +84,18 @@ def cpu_baseline(w, n_freq_sample, max_seconds=30.0):
     done = 0
     t0 = time.perf_counter()
     results = {}
-    for k in range(min(n_freq_sample, w.n_freq)):
+    # frequencies spread over the whole range, the lowest (slowest to
+    # converge) and the highest included
+    ks = sorted({int(round(x)) for x in np.linspace(0, w.n_freq - 1, min(n_freq_sample, w.n_freq))})
+    for k in ks:
         results[k] = oracle.diag_inv_rgf(w.dims, d[k], w.t)
         done += 1
         if time.perf_counter() - t0 > max_seconds:
             break
     dt = time.perf_counter() - t0
     return dict(value=w.n_sites * done / dt, unit="site*freq/s", cores=threads, kind="oracle",
-                sample=f"{done} of {w.n_freq} frequencies of the same {w.dims[0]}x{w.dims[1]} "
+                sample=f"{done} of {w.n_freq} frequencies (k = {sorted(results)}) of the same "
+                       f"{w.dims[0]}x{w.dims[1]} "
                        f"lattice, O2 recursive Green's function, FP64, {dt:.1f} s"), results
 
 
@@ -361,10 +365,17 @@ def main():
             ps.close()
             ms1, nb1, nl1 = r1["kern_ms"][c], r1["kern_bytes"][c], r1["kern_launches"][c]
             a1 = nb1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
+            per_class = {}
+            for ci, name in enumerate(KERNEL_NAMES):
+                m_, b_ = r1["kern_ms"][ci], r1["kern_bytes"][ci]
+                g_ = b_ / (m_ * 1e-3) / 1e9 if m_ > 0 else 0.0
+                per_class[name] = {"GBps": round(g_, 1), "frac": round(g_ / PEAK_HBM_GBS, 4),
+                                   "launches": r1["kern_launches"][ci]}
             roof["standalone"] = {"level_streams": 1, "achieved": round(a1, 1),
                                   "frac": round(a1 / PEAK_HBM_GBS, 4),
                                   "avg_launch_us": round(1000.0 * ms1 / max(nl1, 1), 2),
-                                  "launches": nl1, "solve_s": round(t1, 3)}
+                                  "launches": nl1, "solve_s": round(t1, 3),
+                                  "kernels": per_class}
             log(f"standalone {KERNEL_NAMES[c]}: {a1:.1f} GB/s over {nl1} launches "
                 f"(levels in sequence, {t1:.2f} s)")
 
@@ -395,6 +406,12 @@ def main():
         log(f"max rel err on {len(ref)} sampled frequencies: {err:.3e}")
         if not err <= 1e-6:
             value = 0.0   # only results within 1e-6 of the oracle count
+    # the solver's own check (a direct solve at two sites of every frequency)
+    # must agree as well: it covers the frequencies the oracle did not
+    est = max(r["est_rel_err"] for r in reports)
+    if not est <= 1e-6:
+        log(f"device error estimate {est:.3e} above 1e-6")
+        value = 0.0
 
     # the plain form: one frequency per call, FP64 factors (sampled, extrapolated)
     plain = None
