@@ -7,7 +7,10 @@ Lanczos to full interface rank (truncated ranks do not reach 1e-6).
 One step = one dyson_solve over all 64 frequencies: assembly, subdomain
 factorization and diag(B^{-1}), eight correction levels of bilinear Lanczos
 with inner solves, combine and scatter.  Inputs are resident in HBM before
-the timed region.
+the timed region.  The inner solves stop at relative residual 1e-11, which
+keeps the result about 1e-9 from the oracle (checked on 16 frequencies spread
+over the range, and by the solve's own direct solves at two sites of every
+frequency); only results within 1e-6 count.
 
 Prints one JSON line.  Diagnostics go to stderr.
 """
@@ -130,7 +133,8 @@ def serve_bench(args):
 
     def plan_kw(w):
         return dict(t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
-                    partition=PART_NESTED, precision=prec)
+                    partition=PART_NESTED, precision=prec, inner_tol=args.inner_tol,
+                    lanczos_tol=args.lanczos_tol)
 
     # one after the other, blocking calls (plans made before the clock starts)
     ctx0 = Context(0)
@@ -233,8 +237,10 @@ def main():
                     help="use only the first K frequencies of the workload (0 = all)")
     ap.add_argument("--level-streams", type=int, default=4,
                     help="concurrent correction-level groups (1 = bottom-up, least memory)")
-    ap.add_argument("--inner-tol", type=float, default=1e-14,
-                    help="relative residual of the inner solves")
+    ap.add_argument("--inner-tol", type=float, default=1e-11,
+                    help="relative residual of the inner solves (1e-11: about 1e-9 from "
+                         "the oracle on this workload, inside the paper's one part in 1e8; "
+                         "the library default 1e-14 gives about 1e-11)")
     ap.add_argument("--lanczos-tol", type=float, default=1e-11)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the hot kernels with HIP events")
@@ -416,7 +422,8 @@ def main():
     # the plain form: one frequency per call, FP64 factors (sampled, extrapolated)
     plain = None
     if args.plain_baseline:
-        pp = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=PREC_FP64)
+        pp = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=PREC_FP64,
+                  inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol)
         ks = sorted({0, w.n_freq // 3, (2 * w.n_freq) // 3, w.n_freq - 1})
         secs = []
         for k in ks:
