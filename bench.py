@@ -362,7 +362,7 @@ def main():
             # the same kernel with nothing beside it: one untimed solve with the
             # levels run one after another, so each launch has the GPU alone
             ps = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
-                      inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=1,
+                      inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=2,
                       level_streams=1)
             t0 = time.perf_counter()
             _, r1 = ps.solve(tV, tom, tsig, G, report=True)
