@@ -173,7 +173,7 @@ def serve_bench(args):
     th = threading.Thread(target=submitter, args=(start,))
     th.start()
     th.join()
-    lat, qwait, batches, mismatch = [], [], [], 0
+    lat, qwait, batches, ests, mismatch = [], [], [], [], 0
     for i, h in enumerate(handles):
         G = h.wait()
         rep = h.report()
@@ -183,6 +183,7 @@ def serve_bench(args):
         lat.append(rep["t_total_ms"] / 1000.0)
         qwait.append(rep["t_queue_ms"] / 1000.0)
         batches.append(rep["batches"])
+        ests.append(rep["est_rel_err"])
         mismatch += int(not torch.equal(G, reqs[i]["G_alone"]))
     t_serve = time.perf_counter() - start
     for h in handles:
@@ -205,7 +206,8 @@ def serve_bench(args):
     out = {
         "metric": "served G_ii sites*freqs/sec at rel err <= 1e-6 vs FP64 oracle; "
                   "p50/p99 request latency",
-        "value": work / t_serve if err <= 1e-6 else 0.0, "unit": "site*freq/s", "n_gpus": 1,
+        "value": work / t_serve if err <= 1e-6 and max(ests) <= 1e-6 else 0.0,
+        "unit": "site*freq/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"Poisson stream, {len(reqs)} requests at {args.serve_rate}/s, "
                                f"{args.serve_mix} lattice mix", "slots": args.serve_slots,
@@ -220,7 +222,7 @@ def serve_bench(args):
         "speedup_vs_sequential": t_seq / t_serve,
         "mismatches_vs_alone": mismatch,
         "max_rel_err_sampled": err,
-        "est_rel_err_device": max(r["est_rel_err"] for r in reports),
+        "est_rel_err_device": max(ests),
     }
     print(json.dumps(out), flush=True)
 
@@ -235,7 +237,7 @@ def main():
                     default="square256")
     ap.add_argument("--freqs", type=int, default=0,
                     help="use only the first K frequencies of the workload (0 = all)")
-    ap.add_argument("--level-streams", type=int, default=4,
+    ap.add_argument("--level-streams", type=int, default=3,
                     help="concurrent correction-level groups (1 = bottom-up, least memory)")
     ap.add_argument("--inner-tol", type=float, default=1e-11,
                     help="relative residual of the inner solves (1e-11: about 1e-9 from "
