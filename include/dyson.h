@@ -87,7 +87,7 @@ typedef struct {
   int max_rank;       /* cap on Lanczos steps per domain (truncated rank); 0 = full [0] */
   int extra_steps;    /* steps allowed beyond the interface size m (Sec. II.C):
                          the cap is m + max(extra_steps, ceil(m/8)) [10] */
-  int max_inner_iters;/* iteration cap of each inner solve [2000] */
+  int max_inner_iters;/* iteration cap of each inner solve, 1..1000000 [2000] */
   double inner_tol;   /* relative residual of the inner solves [1e-14] */
   double lanczos_tol; /* stop when |r|_2 <= lanczos_tol*|u|_2 [1e-11] */
   uint64_t seed;      /* seed of the Lanczos start vectors [0x5eed] */

@@ -73,7 +73,8 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
       opts.precision != DYSON_PREC_MIXED16)
     return "unknown precision";
   if (opts.max_rank < 0 || opts.extra_steps < 0) return "max_rank and extra_steps must be >= 0";
-  if (opts.max_inner_iters < 1) return "max_inner_iters must be >= 1 (0 selects the default)";
+  if (opts.max_inner_iters < 1 || opts.max_inner_iters > 1000000)
+    return "max_inner_iters must be in [1, 1000000] (0 selects the default)";
   if (opts.level_streams < 1 || opts.level_streams > 8) return "level_streams must be in [1, 8]";
   if (opts.check_sites < 0 || opts.check_sites > 2) return "check_sites must be in [-1, 2]";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];

@@ -188,12 +188,13 @@ def test_solve_rejects_too_many_frequencies_per_call():
     B.dyson_plan_destroy(plan)
 
 
-def test_plan_rejects_negative_inner_iteration_cap():
+@pytest.mark.parametrize("cap", [-5, 1000001])
+def test_plan_rejects_inner_iteration_cap_out_of_range(cap):
     lat = B.Lattice()
     lat.dim = 2
     lat.L[0], lat.L[1], lat.L[2] = 16, 16, 1
     lat.t, lat.mu = -1.0, 0.5
-    o = B.Opts(8, B.PART_NESTED, 0, 0, 10, -5, 1e-14, 1e-11, 1, 0)
+    o = B.Opts(8, B.PART_NESTED, 0, 0, 10, cap, 1e-14, 1e-11, 1, 0)
     with pytest.raises(B.DysonError) as e:
         B.dyson_plan_create(None, lat, o)
     assert e.value.status == 1
