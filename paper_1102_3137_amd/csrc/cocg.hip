@@ -49,16 +49,33 @@ __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
   return u;
 }
 
-// Sum over the item's tiles of `per` complex partials per unit, fixed order.
+// Sum over the item's tiles of `per` complex partials per unit, fixed order:
+// lane L adds tiles lo+L, lo+L+64, ... in turn, then the wave reduces.  The
+// loads of a chunk of CH tiles per lane go out together (addresses clamped to
+// the range, so every load is valid) and are added in order afterwards: one
+// memory round trip per chunk instead of one per tile.
 __device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
                                          const Unit& u, cd& s0, cd& s1) {
+  constexpr int CH = 4;
   const int lo = a.tlo[u.node], hi = a.thi[u.node];
   s0 = cmk(0.0, 0.0);
   s1 = cmk(0.0, 0.0);
-  for (int tt = lo + u.lane; tt < hi; tt += 64) {
-    const size_t qq = ((size_t)u.k * a.G.T + tt) * per;
-    s0 = cadd(s0, ld(part, qq));
-    if (per == 2) s1 = cadd(s1, ld(part, qq + 1));
+  const size_t kb = (size_t)u.k * a.G.T;
+  for (int t0 = lo + u.lane; t0 < hi; t0 += 64 * CH) {
+    cd v0[CH], v1[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int tt = t0 + 64 * q;
+      const size_t qq = (kb + (tt < hi ? tt : hi - 1)) * per;
+      v0[q] = ld(part, qq);
+      v1[q] = per == 2 ? ld(part, qq + 1) : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (t0 + 64 * q < hi) {
+        s0 = cadd(s0, v0[q]);
+        if (per == 2) s1 = cadd(s1, v1[q]);
+      }
   }
   s0 = wave_sum(s0);
   if (per == 2) s1 = wave_sum(s1);
@@ -84,12 +101,10 @@ struct WaveFactor<float, true> {
       // 32 contiguous bytes, the wave 2 KB per slice
       const float4* f4 = reinterpret_cast<const float4*>(fac + 2 * fbase);
 #pragma unroll
-      for (int y = 0; y < 16; ++y) {
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-        if (y < sy) {
-          a = f4[(size_t)y * 128 + 2 * lane];
-          b = f4[(size_t)y * 128 + 2 * lane + 1];
-        }
+      for (int y = 0; y < 16; ++y) {  // slices y >= sy re-read slice sy-1 (unused)
+        const size_t yy = (size_t)(y < sy ? y : sy - 1);
+        const float4 a = f4[yy * 128 + 2 * lane];
+        const float4 b = f4[yy * 128 + 2 * lane + 1];
         gr[y][0] = __float_as_uint(a.x); gi[y][0] = __float_as_uint(a.y);
         gr[y][1] = __float_as_uint(a.z); gi[y][1] = __float_as_uint(a.w);
         gr[y][2] = __float_as_uint(b.x); gi[y][2] = __float_as_uint(b.y);
@@ -123,11 +138,12 @@ struct WaveFactor<__half, true> {
   __device__ __forceinline__ void load(const __half* fac, size_t fbase, int sx, int sy, int lane) {
     const int i = lane >> 2, c = lane & 3;
     if (sx == 16) {
+      // slices y >= sy are never used by the sweep: they re-read slice sy-1,
+      // so all sixteen loads are unconditional and go out back to back
       const uint4* f4 = reinterpret_cast<const uint4*>(fac + 2 * fbase);
 #pragma unroll
       for (int y = 0; y < 16; ++y) {
-        uint4 a = make_uint4(0u, 0u, 0u, 0u);
-        if (y < sy) a = f4[(size_t)y * 64 + lane];
+        const uint4 a = f4[(size_t)(y < sy ? y : sy - 1) * 64 + lane];
         g[y][0] = a.x;
         g[y][1] = a.y;
         g[y][2] = a.z;
@@ -217,6 +233,21 @@ __device__ __forceinline__ void tile_solve_any(const WaveFactor<F, REG>& f, cons
                                                size_t fbase, cd* zl, const uint8_t* act,
                                                const TileGeom& G, int lane) {
   wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
+}
+
+// One lane's complex value (16 bytes) copied from global memory into LDS
+// without passing through registers: the wave's 64 lanes fill 64 consecutive
+// slots from `row` (lane i writes row[i]).
+__device__ __forceinline__ void lds_copy16(const double* g, cd* row) {
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g),
+                                   (__attribute__((address_space(3))) void*)(row), 16, 0, 0);
+}
+// Waits for every outstanding vector memory access of the wave (vmcnt = 0),
+// which includes the LDS copies; the empty asm keeps the compiler from moving
+// LDS reads above it.
+__device__ __forceinline__ void wait_vm_all() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt not waited on
+  __asm__ volatile("" ::: "memory");
 }
 
 // Item state: 0 open; 1 closed at the start (zero right-hand side or a
@@ -396,11 +427,29 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   const F* fac = (const F*)a.fac;
   const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  __shared__ cd zsh[WAVES][256];
+  __shared__ cd rsh[WAVES][256];
+  __shared__ uint8_t ash[WAVES][256];
+  cd* zl = zsh[u.wave];
+  cd* rl = rsh[u.wave];
+  uint8_t* act = ash[u.wave];
+  // r and s of the tile go straight into the wave's LDS slices (no registers
+  // held), then the factors: both are in flight during the item reduction
+  // instead of r and s waiting for alpha
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    if (l < G.S) {
+      lds_copy16(a.r + 2 * (base + l), rl + 64 * e);
+      lds_copy16(a.s + 2 * (base + l), zl + 64 * e);
+    }
+  }
   WaveFactor<F, REG> f;
-  f.load(fac, fbase, G.sx, G.sy, u.lane);  // issued first: overlaps the item reduction
+  f.load(fac, fbase, G.sx, G.sy, u.lane);
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
+    wait_vm_all();  // the LDS copies land before the wave leaves
     if (it & 1) {  // apply the pending alpha_{i-1} p_{i-1} before closing the item
       const cd ap = ld(a.alph, u.item);
       for (int l = u.lane; l < G.S; l += 64) {
@@ -424,12 +473,7 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
                          (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
   }
   const cd aprev = odd ? ld(a.alph, u.item) : cmk(0.0, 0.0);
-  __shared__ cd zsh[WAVES][256];
-  __shared__ cd rsh[WAVES][256];
-  __shared__ uint8_t ash[WAVES][256];
-  cd* zl = zsh[u.wave];
-  cd* rl = rsh[u.wave];
-  uint8_t* act = ash[u.wave];
+  wait_vm_all();  // r and s are in LDS
   cd rr = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -443,7 +487,7 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
         if (odd)
           st(a.x, base + l,
              cfma(alpha, ld(a.p_new, base + l), cfma(aprev, ld(a.p_old, base + l), ld(a.x, base + l))));
-        rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
+        rv = csub(rl[l], cmul(alpha, zl[l]));
       }
       st(a.r, base + l, rv);
       rr.x += cabs2(rv);
