@@ -317,8 +317,38 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
   }
 }
 
+// Halo of a tile: the sites of the adjacent tiles that its face sites bond
+// to.  Slot h = dir * F + pos, F = s^(D-1) sites per face, pos = the face
+// site's coordinates other than the axis of dir (x fastest).  At most 2*D*F
+// = 96 slots (D = 3, s = 4), so two per lane.
+__device__ __forceinline__ int halo_pos(const TileGeom& G, int a, int x, int y, int z) {
+  const int s = G.edge;
+  if (G.dim == 1) return 0;
+  if (G.dim == 2) return a == 0 ? y : x;
+  return a == 0 ? y + s * z : (a == 1 ? x + s * z : x + s * y);
+}
+// the face site (tile-local index) of slot h, and the direction it faces
+__device__ __forceinline__ int halo_site(const TileGeom& G, int h, int& dir) {
+  const int s = G.edge;
+  const int F = G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s);
+  dir = G.dim == 1 ? h : (G.dim == 2 ? div_edge(G, h) : div_edge(G, div_edge(G, h)));
+  const int pos = h - dir * F;
+  const int a = dir >> 1, c = (dir & 1) ? s - 1 : 0;
+  if (G.dim == 1) return c;
+  if (G.dim == 2) return a == 0 ? c + s * pos : pos + s * c;
+  const int p1 = div_edge(G, pos), p0 = pos - s * p1;
+  const int x = a == 0 ? c : p0, y = a == 0 ? p0 : (a == 1 ? c : p1), z = a == 2 ? c : p1;
+  return x + s * y + s * s * z;
+}
+
 // Convergence test of the previous update, beta = rho_i / rho_{i-1};
-// p_new = z + beta p_old ; s = A_g p_new ; partial mu = p^T s
+// p_new = z + beta p_old ; s = A_g p_new ; partial mu = p^T s.
+// Every load that does not depend on beta goes out before the item
+// reduction: the tile's own p_old, z, d and activity bytes, and the halo
+// (p_old, z and activity of the neighbouring tiles' sites next to this
+// tile), whose p_new = z + beta p_old is formed here as for the own sites
+// (the neighbour tile, when active, belongs to the same domain and so to
+// the same item and beta).
 __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   const Unit u = decode(a);
   if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
@@ -327,33 +357,55 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   const size_t kb = (size_t)u.k * NP;
   const size_t base = kb + (size_t)u.t * G.S;
   const bool lead = u.t == a.tlo[u.node];  // records the item state
-  // the tile's own p_old and z do not depend on beta: their loads go out
-  // before the item reduction, so the two latencies overlap
+  const int s = G.edge;
+  const int H = 2 * G.dim * (G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s));
+  // halo slots h = lane, lane + 64: neighbour tile first (its loads depend on it)
+  int hn[2];
+  size_t hi_[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int h = u.lane + 64 * j;
+    int dir = 0;
+    const int l = halo_site(G, h < H ? h : 0, dir);
+    const int stride = (dir >> 1) == 0 ? 1 : ((dir >> 1) == 1 ? s : s * s);
+    hn[j] = h < H ? G.nbr[u.t * 6 + dir] : -1;
+    // neighbour site index (own face site as a valid stand-in when there is none)
+    const int nl = (dir & 1) ? l - (s - 1) * stride : l + (s - 1) * stride;
+    hi_[j] = (size_t)u.t * G.S + l;
+    if (hn[j] >= 0) hi_[j] = (size_t)hn[j] * G.S + nl;
+  }
   bool ac[4];
-  cd po[4], zo[4];
+  cd po[4], zo[4], dv[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int l = u.lane + 64 * e;
-    ac[e] = false;
-    po[e] = zo[e] = cmk(0.0, 0.0);
-    if (l < G.S) {
-      const size_t p = (size_t)u.t * G.S + l;
-      ac[e] = active(G.kind[p], G.depth[p], a.g);
-      po[e] = ld(a.p_old, base + l);
-      zo[e] = ld(a.z, base + l);
-    }
+    const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
+    ac[e] = active(G.kind[p], G.depth[p], a.g) && l < G.S;
+    po[e] = ld(a.p_old, kb + p);
+    zo[e] = ld(a.z, kb + p);
+    dv[e] = ld(a.d, kb + p);
+  }
+  bool hac[2];
+  cd hpo[2], hz[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    hac[j] = hn[j] >= 0 && active(G.kind[hi_[j]], G.depth[hi_[j]], a.g);
+    hpo[j] = ld(a.p_old, kb + hi_[j]);
+    hz[j] = ld(a.z, kb + hi_[j]);
   }
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
+    const double bn2 = a.st.bn2[u.item];
+    const cd rho_prev = ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item);
     cd rho, rr;
     item_sum(a.partU, 2, a, u, rho, rr);
-    if (a.flush || rr.x <= a.tol2 * a.st.bn2[u.item]) {
+    if (a.flush || rr.x <= a.tol2 * bn2) {
       if (it & 1) {  // the last update was even: x still lacks alpha_{i-1} p_{i-1}
         const cd ap = ld(a.alph, u.item);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int l = u.lane + 64 * e;
-          if (l < G.S && ac[e]) st(a.x, base + l, cfma(ap, po[e], ld(a.x, base + l)));
+          if (ac[e]) st(a.x, base + l, cfma(ap, po[e], ld(a.x, base + l)));
         }
       }
       if (lead && u.lane == 0) {
@@ -362,7 +414,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
       }
       return;
     }
-    beta = cdiv(rho, ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item));
+    beta = cdiv(rho, rho_prev);
     if (lead && u.lane == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
   }
   // profiling: the item's lead wave books the algorithmic bytes of all the
@@ -372,7 +424,9 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
         (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
         ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
   __shared__ cd psh[WAVES][256];
+  __shared__ cd hsh[WAVES][128];
   cd* pl = psh[u.wave];
+  cd* hl = hsh[u.wave];
   cd pn[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -381,6 +435,8 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
     if (l < G.S) st(a.p_new, base + l, pn[e]);
     pl[l] = pn[e];
   }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) hl[u.lane + 64 * j] = hac[j] ? cfma(beta, hpo[j], hz[j]) : cmk(0.0, 0.0);
   wave_sync();
   cd mu = cmk(0.0, 0.0);
 #pragma unroll
@@ -391,21 +447,21 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
       st(a.s, base + l, cmk(0.0, 0.0));
       continue;
     }
+    const int q1 = div_edge(G, l), q2 = div_edge(G, q1);
+    const int x = l - s * q1, y = q1 - s * q2, z = q2;
     cd nb = cmk(0.0, 0.0);
     for (int dir = 0; dir < 2 * G.dim; ++dir) {
-      int nt, nl;
-      if (!site_nbr(G, u.t, l, dir, nt, nl)) continue;
-      if (nt == u.t) {
-        nb = cadd(nb, pl[nl]);  // inactive sites hold 0 in pl
+      const int ax = dir >> 1, up = dir & 1;
+      const int c = ax == 0 ? x : (ax == 1 ? y : z);
+      const int stride = ax == 0 ? 1 : (ax == 1 ? s : s * s);
+      if (up ? (c < s - 1) : (c > 0)) {
+        nb = cadd(nb, pl[up ? l + stride : l - stride]);  // inactive sites hold 0 in pl
       } else {
-        // p_new at a site of a neighbouring tile (the same domain when
-        // active); its values are read with the flags and masked after
-        const size_t np = (size_t)nt * G.S + nl;
-        const cd pv = ld(a.p_old, kb + np), zv = ld(a.z, kb + np);
-        if (active(G.kind[np], G.depth[np], a.g)) nb = cadd(nb, cfma(beta, pv, zv));
+        const int F = G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s);
+        nb = cadd(nb, hl[dir * F + halo_pos(G, ax, x, y, z)]);  // 0 without a neighbour
       }
     }
-    const cd sv = cfma(ld(a.d, base + l), pn[e], cscale(nb, G.t));
+    const cd sv = cfma(dv[e], pn[e], cscale(nb, G.t));
     st(a.s, base + l, sv);
     mu = cfma(pn[e], sv, mu);
   }
