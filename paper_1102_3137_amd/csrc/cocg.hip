@@ -56,7 +56,7 @@ __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
 // memory round trip per chunk instead of one per tile.
 __device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
                                          const Unit& u, cd& s0, cd& s1) {
-  constexpr int CH = 4;
+  constexpr int CH = 2;
   const int lo = a.tlo[u.node], hi = a.thi[u.node];
   s0 = cmk(0.0, 0.0);
   s1 = cmk(0.0, 0.0);
@@ -500,25 +500,44 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
       lds_copy16(a.s + 2 * (base + l), zl + 64 * e);
     }
   }
+  // the activity bytes of the lane's sites and the item's rho, loaded with
+  // the factors; complex64 register factors take 128 VGPRs, so there they
+  // are loaded after the reduction instead of being held across it
+  constexpr bool kEarly = !(REG && sizeof(F) == 4);
+  unsigned acm = 0;  // bit e: site lane + 64 e is active in graph g
+  cd rho;
+  auto load_item_state = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = u.lane + 64 * e;
+      const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
+      const bool on = active(G.kind[p], G.depth[p], a.g);
+      acm |= (on && l < G.S) ? (1u << e) : 0u;
+    }
+    rho = ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item);
+  };
+  if constexpr (kEarly) load_item_state();
   WaveFactor<F, REG> f;
   f.load(fac, fbase, G.sx, G.sy, u.lane);
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
+  if constexpr (!kEarly) load_item_state();
+  const bool odd = it & 1;
   if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
     wait_vm_all();  // the LDS copies land before the wave leaves
-    if (it & 1) {  // apply the pending alpha_{i-1} p_{i-1} before closing the item
+    if (odd) {  // apply the pending alpha_{i-1} p_{i-1} before closing the item
       const cd ap = ld(a.alph, u.item);
-      for (int l = u.lane; l < G.S; l += 64) {
-        const size_t p = (size_t)u.t * G.S + l;
-        if (active(G.kind[p], G.depth[p], a.g))
-          st(a.x, base + l, cfma(ap, ld(a.p_old, base + l), ld(a.x, base + l)));
-      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if ((acm >> e) & 1u) {
+          const size_t i = base + u.lane + 64 * e;
+          st(a.x, i, cfma(ap, ld(a.p_old, i), ld(a.x, i)));
+        }
     }
     if (u.t == a.tlo[u.node] && u.lane == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
-  const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
-  const bool odd = it & 1;
+  const cd alpha = cdiv(rho, mu);
   if (u.t == a.tlo[u.node] && u.lane == 0) {
     if (!odd) st(a.alph, u.item, alpha);
     // algorithmic bytes: r, s read and r, z written every iteration; x read and
@@ -528,23 +547,21 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
                         ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
                          (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
   }
-  const cd aprev = odd ? ld(a.alph, u.item) : cmk(0.0, 0.0);
+  // complex64 register factors: the deferred x update in this loop (alpha
+  // is then dead during the sweep); otherwise after the sweep, below
+  const cd aprev_in_loop = (!kEarly && odd) ? ld(a.alph, u.item) : cmk(0.0, 0.0);
   wait_vm_all();  // r and s are in LDS
   cd rr = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int l = u.lane + 64 * e;
+    const uint8_t ac = (acm >> e) & 1u;
     cd rv = cmk(0.0, 0.0);
-    uint8_t ac = 0;
     if (l < G.S) {
-      const size_t p = (size_t)u.t * G.S + l;
-      ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
-      if (ac) {
-        if (odd)
-          st(a.x, base + l,
-             cfma(alpha, ld(a.p_new, base + l), cfma(aprev, ld(a.p_old, base + l), ld(a.x, base + l))));
-        rv = csub(rl[l], cmul(alpha, zl[l]));
-      }
+      if (!kEarly && odd && ac)
+        st(a.x, base + l,
+           cfma(alpha, ld(a.p_new, base + l), cfma(aprev_in_loop, ld(a.p_old, base + l), ld(a.x, base + l))));
+      if (ac) rv = csub(rl[l], cmul(alpha, zl[l]));
       st(a.r, base + l, rv);
       rr.x += cabs2(rv);
     }
@@ -569,6 +586,26 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
     const size_t q = ((size_t)u.k * G.T + u.t) * 2;
     st(a.partU, q, rz);
     st(a.partU, q + 1, rr);
+  }
+  // the deferred solution update x += alpha_{i-1} p_{i-1} + alpha_i p_i,
+  // after the sweep (nothing in it reads x); the loads of the four sites go
+  // out together (clamped addresses, always valid)
+  if (kEarly && odd) {
+    __asm__ volatile("" ::: "memory");  // keeps these loads below the sweep
+    const cd aprev = ld(a.alph, u.item);
+    cd xv[4], pn[4], po[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = u.lane + 64 * e;
+      const size_t i = base + (l < G.S ? l : G.S - 1);
+      xv[e] = ld(a.x, i);
+      pn[e] = ld(a.p_new, i);
+      po[e] = ld(a.p_old, i);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((acm >> e) & 1u)
+        st(a.x, base + u.lane + 64 * e, cfma(alpha, pn[e], cfma(aprev, po[e], xv[e])));
   }
 }
 
