@@ -795,9 +795,8 @@ __global__ __launch_bounds__(256) void k_cocg_init_planes(CocgLaunch a,
   }
 }
 
-// The stencil launch of k_cocg_stencil, one thread per site.  Values of a
-// neighbouring tile are read together with its activity flags and masked
-// afterwards, so the loads do not wait on the flags.
+// The stencil launch of k_cocg_stencil, one thread per site and one halo
+// slot per thread (6 s^2 <= 216 slots).
 __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
   const Unit u = decode_wg(a);
   if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
@@ -806,24 +805,40 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
   const size_t kb = (size_t)u.k * NP;
   const size_t base = kb + (size_t)u.t * G.S;
   const bool lead = u.t == a.tlo[u.node];
+  const int s = G.edge;
+  const int F = G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s);
+  const int H = 2 * G.dim * F;  // <= 216 halo slots (s = 6): one per thread
+  const int l = threadIdx.x;
+  // as in k_cocg_stencil: the own site's p_old, z, d and activity and the
+  // thread's halo slot go out before the item reduction
+  const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
+  const bool ac = active(G.kind[p], G.depth[p], a.g) && l < G.S;
+  const cd po = ld(a.p_old, kb + p), zo = ld(a.z, kb + p), dv = ld(a.d, kb + p);
+  int hdir = 0;
+  const int hsite = halo_site(G, l < H ? l : 0, hdir);
+  const int hstride = (hdir >> 1) == 0 ? 1 : ((hdir >> 1) == 1 ? s : s * s);
+  const int hn = l < H ? G.nbr[u.t * 6 + hdir] : -1;
+  const size_t hp = hn >= 0 ? (size_t)hn * G.S + ((hdir & 1) ? hsite - (s - 1) * hstride
+                                                               : hsite + (s - 1) * hstride)
+                            : (size_t)u.t * G.S + hsite;
+  const bool hac = hn >= 0 && active(G.kind[hp], G.depth[hp], a.g);
+  const cd hpo = ld(a.p_old, kb + hp), hz = ld(a.z, kb + hp);
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
+    const double bn2 = a.st.bn2[u.item];
+    const cd rho_prev = ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item);
     cd rho, rr;
     item_sum(a.partU, 2, a, u, rho, rr);
-    if (a.flush || rr.x <= a.tol2 * a.st.bn2[u.item]) {
-      const int l = threadIdx.x;
-      if ((it & 1) && l < G.S) {  // pending alpha_{i-1} p_{i-1} of the deferred x update
-        const size_t p = (size_t)u.t * G.S + l;
-        if (active(G.kind[p], G.depth[p], a.g))
-          st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
-      }
+    if (a.flush || rr.x <= a.tol2 * bn2) {
+      if ((it & 1) && ac)  // pending alpha_{i-1} p_{i-1} of the deferred x update
+        st(a.x, base + l, cfma(ld(a.alph, u.item), po, ld(a.x, base + l)));
       if (lead && threadIdx.x == 0) {
         a.st.done[u.item] = stencil_mark(it);
         a.st.iters[u.item] = it;
       }
       return;
     }
-    beta = cdiv(rho, ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item));
+    beta = cdiv(rho, rho_prev);
     if (lead && threadIdx.x == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
   }
   if (a.wctr && lead && threadIdx.x == 0)
@@ -831,35 +846,28 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
         (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
         ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
   __shared__ cd pl[256];
-  const int l = threadIdx.x;
-  bool ac = false;
-  cd pn = cmk(0.0, 0.0);
-  if (l < G.S) {
-    const size_t p = (size_t)u.t * G.S + l;
-    ac = active(G.kind[p], G.depth[p], a.g);
-    if (ac) pn = cfma(beta, ld(a.p_old, base + l), ld(a.z, base + l));
-    st(a.p_new, base + l, pn);
-  }
+  __shared__ cd hl[256];
+  const cd pn = ac ? cfma(beta, po, zo) : cmk(0.0, 0.0);
+  if (l < G.S) st(a.p_new, base + l, pn);
   pl[l] = pn;
+  hl[l] = hac ? cfma(beta, hpo, hz) : cmk(0.0, 0.0);
   __syncthreads();
   cd mu = cmk(0.0, 0.0);
   if (l < G.S) {
     if (!ac) {
       st(a.s, base + l, cmk(0.0, 0.0));
     } else {
+      const int q1 = div_edge(G, l), q2 = div_edge(G, q1);
+      const int x = l - s * q1, y = q1 - s * q2, z = q2;
       cd nb = cmk(0.0, 0.0);
       for (int dir = 0; dir < 2 * G.dim; ++dir) {
-        int nt, nl;
-        if (!site_nbr(G, u.t, l, dir, nt, nl)) continue;
-        if (nt == u.t) {
-          nb = cadd(nb, pl[nl]);
-        } else {
-          const size_t np = (size_t)nt * G.S + nl;
-          const cd po = ld(a.p_old, kb + np), zo = ld(a.z, kb + np);
-          if (active(G.kind[np], G.depth[np], a.g)) nb = cadd(nb, cfma(beta, po, zo));
-        }
+        const int ax = dir >> 1, up = dir & 1;
+        const int c = ax == 0 ? x : (ax == 1 ? y : z);
+        const int stride = ax == 0 ? 1 : (ax == 1 ? s : s * s);
+        if (up ? (c < s - 1) : (c > 0)) nb = cadd(nb, pl[up ? l + stride : l - stride]);
+        else nb = cadd(nb, hl[dir * F + halo_pos(G, ax, x, y, z)]);
       }
-      const cd sv = cfma(ld(a.d, base + l), pn, cscale(nb, G.t));
+      const cd sv = cfma(dv, pn, cscale(nb, G.t));
       st(a.s, base + l, sv);
       mu = cmul(pn, sv);
     }
@@ -875,20 +883,29 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
   if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
+  // as in the wave kernel: everything that does not depend on alpha (the
+  // site's r, s and activity, the item's rho, the factors) goes out before
+  // the item reduction; the deferred x update follows the sweep
+  const int l = threadIdx.x;
+  const int lc = l < G.S ? l : G.S - 1;  // clamped: always a valid site
+  const size_t p = (size_t)u.t * G.S + lc;
+  const uint8_t ac = (active(G.kind[p], G.depth[p], a.g) && l < G.S) ? 1 : 0;
+  const cd r0 = ld(a.r, base + lc), s0 = ld(a.s, base + lc);
+  const cd rho = ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item);
+  const F* fac = (const F*)a.fac;
+  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
+  PlaneFactor<F> f;
+  f.load(fac, fbase, G.sx, G.sy, threadIdx.x >> 2, threadIdx.x & 3);
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
+  const bool odd = it & 1;
   if (cabs2(mu) == 0.0) {
-    const int l = threadIdx.x;
-    if ((it & 1) && l < G.S) {
-      const size_t p = (size_t)u.t * G.S + l;
-      if (active(G.kind[p], G.depth[p], a.g))
-        st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
-    }
+    if (odd && ac)
+      st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
     if (u.t == a.tlo[u.node] && threadIdx.x == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
-  const cd alpha = cdiv(ld(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item), mu);
-  const bool odd = it & 1;
+  const cd alpha = cdiv(rho, mu);
   if (u.t == a.tlo[u.node] && threadIdx.x == 0) {
     if (!odd) st(a.alph, u.item, alpha);
     if (a.wctr)
@@ -896,25 +913,11 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
                         ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
                          (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
   }
-  const cd aprev = odd ? ld(a.alph, u.item) : cmk(0.0, 0.0);
   __shared__ cd zl[256];
   __shared__ uint8_t act[256];
-  const F* fac = (const F*)a.fac;
-  const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
-  PlaneFactor<F> f;
-  f.load(fac, fbase, G.sx, G.sy, threadIdx.x >> 2, threadIdx.x & 3);  // overlaps the vector loads
-  const int l = threadIdx.x;
   cd rv = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
-  uint8_t ac = 0;
   if (l < G.S) {
-    const size_t p = (size_t)u.t * G.S + l;
-    ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
-    if (ac) {
-      if (odd)
-        st(a.x, base + l,
-           cfma(alpha, ld(a.p_new, base + l), cfma(aprev, ld(a.p_old, base + l), ld(a.x, base + l))));
-      rv = csub(ld(a.r, base + l), cmul(alpha, ld(a.s, base + l)));
-    }
+    if (ac) rv = csub(r0, cmul(alpha, s0));
     st(a.r, base + l, rv);
     rr.x = cabs2(rv);
   }
@@ -933,6 +936,9 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
     st(a.partU, q, rz);
     st(a.partU, q + 1, rr);
   }
+  if (odd && ac)  // x += alpha_{i-1} p_{i-1} + alpha_i p_i
+    st(a.x, base + l,
+       cfma(alpha, ld(a.p_new, base + l), cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l))));
 }
 
 // One workgroup: convergence bookkeeping after launch `it` (it = 0 follows
