@@ -17,7 +17,7 @@
 // partials of their item in a fixed order (so every wave derives the same
 // scalars, deterministically); the wave on the item's first tile records
 // the item state.  An iteration is two launches (stencil, update); the host
-// polls convergence through a one-workgroup check kernel.
+// polls convergence through a check kernel (one wave per item).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,14 +54,14 @@ __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
 // loads of a chunk of CH tiles per lane go out together (addresses clamped to
 // the range, so every load is valid) and are added in order afterwards: one
 // memory round trip per chunk instead of one per tile.
-__device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
-                                         const Unit& u, cd& s0, cd& s1) {
+__device__ __forceinline__ void item_sum_of(const double* part, int per, const CocgLaunch& a,
+                                            int k, int node, int lane, cd& s0, cd& s1) {
   constexpr int CH = 2;
-  const int lo = a.tlo[u.node], hi = a.thi[u.node];
+  const int lo = a.tlo[node], hi = a.thi[node];
   s0 = cmk(0.0, 0.0);
   s1 = cmk(0.0, 0.0);
-  const size_t kb = (size_t)u.k * a.G.T;
-  for (int t0 = lo + u.lane; t0 < hi; t0 += 64 * CH) {
+  const size_t kb = (size_t)k * a.G.T;
+  for (int t0 = lo + lane; t0 < hi; t0 += 64 * CH) {
     cd v0[CH], v1[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
@@ -79,6 +79,10 @@ __device__ __forceinline__ void item_sum(const double* part, int per, const Cocg
   }
   s0 = wave_sum(s0);
   if (per == 2) s1 = wave_sum(s1);
+}
+__device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
+                                         const Unit& u, cd& s0, cd& s1) {
+  item_sum_of(part, per, a, u.k, u.node, u.lane, s0, s1);
 }
 
 // ---------------------------------------------------------- tile solve
@@ -941,41 +945,44 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
        cfma(alpha, ld(a.p_new, base + l), cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l))));
 }
 
-// One workgroup: convergence bookkeeping after launch `it` (it = 0 follows
-// the initialisation) and the number of items still open.
+// Convergence bookkeeping after launch `it` (it = 0 follows the
+// initialisation) and the number of items still open, added into *open
+// (zeroed by the launcher).  One wave per item, reducing the item's partials
+// in the same order as item_sum in the other kernels, so its convergence
+// test agrees with the stencil's bit for bit.
 __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* __restrict__ open) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
+  __shared__ int cnt[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + wave;
   int mine = 0;
-  for (int item = threadIdx.x; item < a.n_items; item += blockDim.x) {
+  if (item < a.n_items) {
     const int k = item / a.n_nodes, node = item % a.n_nodes;
     if (a.item_skip && a.item_skip[item]) {
-      a.st.done[item] = 1;
-      continue;
-    }
-    if (it > 0 && a.st.done[item]) continue;
-    cd s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
-    for (int t = a.tlo[node]; t < a.thi[node]; ++t) {
-      const size_t q = ((size_t)k * a.G.T + t) * 2;
-      s0 = cadd(s0, ld(a.partU, q));
-      s1 = cadd(s1, ld(a.partU, q + 1));
-    }
-    if (it == 0) {
-      a.st.bn2[item] = s1.x;
-      st(a.rho2, item, s0);
-      a.st.iters[item] = 0;
-      a.st.done[item] = (s1.x > 0.0) ? 0 : 1;
-      mine += a.st.done[item] == 0;
-    } else {
-      // converged items are marked (and their deferred x update applied) by
-      // the next stencil launch; here they only stop counting as open
-      mine += !(s1.x <= a.tol2 * a.st.bn2[item]);
+      if (lane == 0) a.st.done[item] = 1;
+    } else if (it == 0 || !a.st.done[item]) {
+      cd s0, s1;
+      item_sum_of(a.partU, 2, a, k, node, lane, s0, s1);
+      if (it == 0) {
+        if (lane == 0) {
+          a.st.bn2[item] = s1.x;
+          st(a.rho2, item, s0);
+          a.st.iters[item] = 0;
+          a.st.done[item] = (s1.x > 0.0) ? 0 : 1;
+        }
+        mine = s1.x > 0.0;
+      } else {
+        // converged items are marked (and their deferred x update applied)
+        // by the next stencil launch; here they only stop counting as open
+        mine = !(s1.x <= a.tol2 * a.st.bn2[item]);
+      }
     }
   }
-  atomicAdd(&cnt, mine);
+  if (lane == 0) cnt[wave] = mine;
   __syncthreads();
-  if (threadIdx.x == 0) *open = cnt;
+  if (threadIdx.x == 0) {
+    const int c = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    if (c) atomicAdd(open, c);
+  }
 }
 
 // profiling: fold per-item byte counts [classes][n] into tot[class], zeroing them
@@ -1031,7 +1038,8 @@ void launch_prof_collect(unsigned long long* per_item, int n, int classes, int f
   k_prof_collect<<<1, 256, 0, s>>>(per_item, n, classes, first_class, tot);
 }
 void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
-  k_cocg_check<<<1, 256, 0, s>>>(L, it, open);
+  (void)hipMemsetAsync(open, 0, sizeof(int), s);
+  if (L.n_items > 0) k_cocg_check<<<(unsigned)((L.n_items + 3) / 4), 256, 0, s>>>(L, it, open);
 }
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
   if (L.G.sx > 16) {
