@@ -279,24 +279,23 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
   cd* zl = zsh[u.wave];
   uint8_t* act = ash[u.wave];
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
-  cd rv[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int l = u.lane + 64 * e;
-    rv[e] = cmk(0.0, 0.0);
-    uint8_t ac = 0;
-    if (l < G.S) {
-      const size_t p = (size_t)u.t * G.S + l;
-      ac = active(G.kind[p], G.depth[p], a.g) ? 1 : 0;
-      if (ac) rv[e] = ld(b, base + l);
-    }
-    act[l] = ac;
-    zl[l] = rv[e];
-  }
+  // factors, activity bytes and b all go out before anything waits
   const F* fac = (const F*)a.fac;
   const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
   WaveFactor<F, REG> f;
   f.load(fac, fbase, G.sx, G.sy, u.lane);
+  cd rv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    const int lc = l < G.S ? l : G.S - 1;  // clamped: always a valid site
+    const size_t p = (size_t)u.t * G.S + lc;
+    const bool ac = active(G.kind[p], G.depth[p], a.g) && l < G.S;
+    const cd bv = ld(b, base + lc);
+    rv[e] = ac ? bv : cmk(0.0, 0.0);
+    act[l] = ac ? 1 : 0;
+    zl[l] = rv[e];
+  }
   tile_solve_any<F, REG>(f, fac, fbase, zl, act, G, u.lane);
   cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
 #pragma unroll
