@@ -215,7 +215,7 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
 
 /* Measured choice of the tile shape: for each candidate leaf edge (8, 12, 16
  * on chains and squares; 4, 5, 6 on cubes; periodic axes keep only edges that
- * divide them) and level-stream count (1, 4), a plan solves the probe inputs
+ * divide them) and level-stream count (1, 3, 4), a plan solves the probe inputs
  * (K frequencies, device pointers as in dyson_solve) once after its
  * workspace is allocated; the fastest wins.  *best = base (NULL: defaults)
  * with leaf_edge and level_streams set; *rate = its site*freq/s.  The probe

@@ -1040,7 +1040,7 @@ dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyso
   if (!d_V || !d_omega || !d_sigma) return fail(DYSON_EINVAL, "null input pointer");
   const dyson_opts b0 = merge_opts(base);
   std::vector<int> edges = (lat->dim == 3) ? std::vector<int>{4, 5, 6} : std::vector<int>{8, 12, 16};
-  const int streams[2] = {1, 4};
+  const int streams[3] = {1, 3, 4};
   long long n = 1;
   for (int a = 0; a < 3; ++a) n *= std::max(1, lat->L[a]);
   HIPC(hipSetDevice(ctx->device));
