@@ -88,10 +88,14 @@ def _dense_X_apply(w, d_row, p, level, q):
     return u
 
 
+# tile shapes for the inner-solve kernels' halo slots (2 D s^(D-1) per tile):
+# 64 (16^2), 32 (8^2), 48 (12^2, 144 sites), 2 (chains), 96 (4^3, two slots
+# per lane), 54 (3^3), 24 (2^3), and the workgroup kernels' 150 (5^3), 216 (6^3)
 @pytest.mark.parametrize("dims,s,part", [((32, 32), 16, 0), ((32, 32), 16, 1), ((37, 29), 8, 0),
                                          ((5, 5), 3, 1), ((40,), 8, 0), ((9, 8, 7), 4, 0),
                                          ((11, 9, 7), 4, 1), ((12, 11, 10), 6, 0),
-                                         ((11, 10, 9), 5, 1)])
+                                         ((11, 10, 9), 5, 1), ((36, 26), 12, 0), ((50,), 16, 0),
+                                         ((7, 6, 5), 3, 0), ((6, 5, 6), 2, 1)])
 def test_xmatvec(dims, s, part):
     w = _case(dims, K=2)
     V, om, sig, tV, tom, tsig = device_inputs(w)
