@@ -309,6 +309,8 @@ PERIODIC_CASES = [
     ((40,), 8, (1,)),            # ring
     ((12, 12, 12), 6, (1, 1, 1)),  # 3-D torus, plane-slice kernels
     ((12, 8, 8), 4, (0, 1, 1)),
+    ((4, 8, 8), 4, (1, 0, 0)),   # one tile wide along x: the halo slot wraps onto its own tile
+    ((5, 10, 10), 5, (1, 0, 1)),  # the same for the plane-slice kernels
 ]
 
 
