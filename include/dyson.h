@@ -99,7 +99,11 @@ typedef struct {
                          groups, each on its own HIP stream and workspace,
                          1 = one after the other, bottom-up.  Results do not
                          depend on timing; the group sums are added in a fixed
-                         order [4] */
+                         order [4].  HIP runs streams that share a hardware
+                         queue one after another: with several solves or
+                         server slots at once, give the process enough queues
+                         (GPU_MAX_HW_QUEUES, read when the HIP runtime starts;
+                         4 by default) */
   int check_sites;    /* sampled error estimate (report.est_rel_err): at this
                          many fixed sites (0..2; the first on the top-level
                          interface, the second inside a subdomain) the exact
