@@ -124,7 +124,9 @@ typedef struct {
   int truncated;            /* 1 if any (domain, frequency) stopped at its step cap
                                (max_rank or m + extra) before the Krylov space of X
                                was exhausted: that result is not full rank */
-  /* per-kernel timing (profile=1), HIP events on the call's stream:
+  /* per-kernel timing (profile=1), HIP events on the call's stream around a
+   * fixed pseudo-random one in sixteen of a class's launches, scaled to all
+   * of them (kern_launches and kern_bytes count every launch):
    * 0 = inner-solve update + tile preconditioner (k_cocg_update),
    * 1 = inner-solve stencil (k_cocg_stencil), 2 = re-orthogonalization
    * update (k_cgs_update), 3 = re-orthogonalization products (k_cgs_dot) */

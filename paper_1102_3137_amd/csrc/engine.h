@@ -38,6 +38,7 @@ struct Prof {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
   size_t used = 0;
   long long launches[4] = {0, 0, 0, 0};
+  long long timed[4] = {0, 0, 0, 0};  // launches with events around them
   double bytes[4] = {0, 0, 0, 0};
   hipEvent_t get();
   void reset();

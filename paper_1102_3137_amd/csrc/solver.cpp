@@ -70,7 +70,7 @@ hipEvent_t Prof::get() {
 void Prof::reset() {
   used = 0;
   marks.clear();
-  for (int c = 0; c < 4; ++c) launches[c] = 0, bytes[c] = 0;
+  for (int c = 0; c < 4; ++c) launches[c] = 0, timed[c] = 0, bytes[c] = 0;
 }
 Prof::~Prof() {
   for (auto e : pool) (void)hipEventDestroy(e);
@@ -317,14 +317,23 @@ struct Run {
   hipStream_t s;
   const HostPlan& P() const { return p->hp; }
 
-  // Time a launch when profiling: class c, algorithmic bytes b.
+  // Time a launch when profiling, class c.  profile = 1: the inner-solve
+  // update kernel only (the dominant kernel); profile >= 2: every class.
+  // Events around every launch cost about 4% of a solve, so a fixed
+  // pseudo-random one in sixteen of a class's launches is timed (Knuth's
+  // multiplicative hash of the launch index) and the report scales the sample
+  // to all launches; the algorithmic bytes are counted for every launch.
   template <typename Fn>
   void timed(int c, Fn fn) {
     Prof& pr = w->prof;
-    // profile = 1: events around the inner-solve update kernel only (the
-    // dominant kernel); profile >= 2: around every timed kernel class
-    if (!pr.on || (P().opts.profile < 2 && c != 0)) {
-      if (pr.on) pr.launches[c] += 1;
+    if (!pr.on) {
+      fn();
+      return;
+    }
+    const unsigned long long n = (unsigned long long)pr.launches[c]++;
+    const bool sample = (P().opts.profile >= 2 || c == 0) &&
+                        ((uint32_t)(n * 2654435761ull) >> 28) == 0;
+    if (!sample) {
       fn();
       return;
     }
@@ -333,7 +342,7 @@ struct Run {
     fn();
     (void)hipEventRecord(b, s);
     pr.marks.push_back({c, {a, b}});
-    pr.launches[c] += 1;
+    pr.timed[c] += 1;
   }
 
   dyson_status count_open(const int* flags, int n, int* out) {
@@ -768,12 +777,16 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
         Work* gw = (g == 0) ? w : w->sub[g - 1].get();
         unsigned long long wb[8];
         HIPC(hipMemcpy(wb, gw->d_prof, sizeof(wb), hipMemcpyDeviceToHost));
+        double ms_c[4] = {0, 0, 0, 0};
         for (auto& m : gw->prof.marks) {
           float ms = 0;
           if (hipEventElapsedTime(&ms, m.second.first, m.second.second) == hipSuccess)
-            rep->kern_ms[m.first] += ms;
+            ms_c[m.first] += ms;
         }
         for (int c = 0; c < 4; ++c) {
+          // the timed sample scaled to all of the class's launches
+          if (gw->prof.timed[c] > 0)
+            rep->kern_ms[c] += ms_c[c] * (double)gw->prof.launches[c] / (double)gw->prof.timed[c];
           rep->kern_launches[c] += gw->prof.launches[c];
           rep->kern_bytes[c] += (double)wb[c];
         }
