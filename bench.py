@@ -420,6 +420,12 @@ def main():
     if not est <= 1e-6:
         log(f"device error estimate {est:.3e} above 1e-6")
         value = 0.0
+    # a (domain, frequency) item stopped by its step cap before exhaustion is
+    # not a full-rank result: the step does not count
+    capped = max(r["capped_items"] for r in reports)
+    if capped:
+        log(f"{capped} (domain, frequency) items hit their Lanczos step cap")
+        value = 0.0
 
     # the plain form: one frequency per call, FP64 factors (sampled, extrapolated)
     plain = None
@@ -461,6 +467,7 @@ def main():
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "max_rel_err_sampled": err,
         "est_rel_err_device": max(r["est_rel_err"] for r in reports),
+        "capped_items": capped,
         "plain_fp64_per_frequency": plain,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -50,7 +50,11 @@ typedef enum {
   DYSON_ENOCONV = 4,     /* an inner solve hit its iteration cap */
   DYSON_EDEVICE = 5,     /* HIP runtime error */
   DYSON_EUNSUPPORTED = 6,/* valid request this build does not implement */
-  DYSON_EBUSY = 7,       /* object still in use (a plan with live requests) */
+  DYSON_EBUSY = 7,       /* object still in use (a plan with live requests, a
+                            context with live plans).  Admission never refuses a
+                            request: one that does not fit the HBM budget waits
+                            in the queue until memory frees up, or fails with
+                            DYSON_ENOMEM if not even one frequency of it fits */
   DYSON_ECANCELLED = 8,  /* the request was cancelled */
   DYSON_ETIMEOUT = 9     /* dyson_wait returned before the request finished */
 } dyson_status;
@@ -75,13 +79,19 @@ enum { DYSON_PREC_FP64 = 0, DYSON_PREC_MIXED = 1, DYSON_PREC_MIXED16 = 2 };
  * the defaults given in brackets. */
 typedef struct {
   int leaf_edge;      /* subdomain edge s: separators at p with (p+1)%s==0 [16];
-                         2..16 (chain, square), 2..6 (cubic: tiles of s^3 <= 216 sites) */
+                         2..16 (chain, square), 2..6 (cubic: tiles of s^3 <= 216 sites).
+                         0 takes the default: a plan is built before any input
+                         exists, so the measured choice comes from dyson_autotune
+                         on probe frequencies, whose result is then passed here */
   int partition;      /* DYSON_PART_NESTED: recursive bisection, alternating axes
                          (end of Sec. II.C); DYSON_PART_SINGLE: one level with
                          every separator at once (Fig. 1) [NESTED] */
   int precision;      /* DYSON_PREC_FP64; DYSON_PREC_MIXED: complex64 subdomain
                          factors in the inner preconditioner; DYSON_PREC_MIXED16:
-                         complex32 (FP16 pairs) factors there.  Residuals, the
+                         complex32 (FP16 pairs) factors there; it needs
+                         Im(z_k - Sigma_i) >= 2^-14 (the factor entries, bounded
+                         by 1 / min Im H_ii, must fit FP16), else the solve
+                         returns DYSON_EUNSUPPORTED.  Residuals, the
                          preconditioner arithmetic, Lanczos, re-orthogonalization
                          and the diagonal stay FP64 in every mode [FP64] */
   int max_rank;       /* cap on Lanczos steps per domain (truncated rank); 0 = full [0] */
@@ -110,6 +120,21 @@ typedef struct {
                          G_ii = e_i^T H^{-1} e_i is also computed by solving
                          H x = e_i directly (eq. (14)) with the inner solver,
                          for every frequency; -1 = none [2] */
+  int fault_step;     /* test hook for the breakdown path (Sec. II.A: the bilinear
+                         "norm" r^T r can vanish): when > 0, every (domain,
+                         frequency) item still open after fault_step Lanczos steps
+                         is declared broken down at that step on its first
+                         fault_attempts attempts, as if |r^T r| had vanished; the
+                         item is then redone from a fresh start vector (report.
+                         restarts), and DYSON_EBREAKDOWN results once the attempts
+                         (3) are used up.  0 = off [0] */
+  int fault_attempts; /* attempts on which fault_step trips, 0..3 [0] */
+  double breakdown_tol; /* serious-breakdown threshold of the bilinear form: an
+                         item whose new residual has |r^T r| <= breakdown_tol |r|_2^2
+                         (so the next basis vector would have |q|_2^2 >=
+                         1/breakdown_tol, amplifying rounding by as much) is
+                         redone from a fresh start vector; each later attempt
+                         uses a 100x smaller threshold [1e-4] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */
@@ -142,6 +167,8 @@ typedef struct {
                                and frequencies, between G_ii and the direct solve
                                of H x = e_i (opts.check_sites); 0 when no check
                                ran (no correction level, or check_sites = -1) */
+  int capped_items;         /* (domain, frequency) items stopped by their step cap
+                               before exhaustion (truncated = capped_items > 0) */
 } dyson_report;
 
 typedef struct dyson_ctx dyson_ctx;
@@ -195,6 +222,13 @@ dyson_status dyson_plan_get_info(const dyson_plan* plan, dyson_plan_info* info);
 dyson_status dyson_plan_get_maps(const dyson_plan* plan, int* h_depth,
                                  int* h_is_sep, int* h_tile);
 
+/* Interface size m and Lanczos step cap of every correction domain of a
+ * level (domains in the order of dyson_correct_level's h_steps): the cap is
+ * m + max(extra_steps, ceil(m/8)), or max_rank when that is smaller; a full-rank
+ * domain takes between m and cap steps (eqs. (8)-(9): X has rank m).  Either
+ * output may be NULL; each has dyson_plan_info.n_nodes[level] entries. */
+dyson_status dyson_plan_get_domains(const dyson_plan* plan, int level, int* h_m, int* h_cap);
+
 /* Device memory a dyson_solve over K frequencies will allocate (bytes); the
  * serving slots hold the same per batch of K frequencies. */
 dyson_status dyson_footprint(const dyson_plan* plan, int K, size_t* bytes);
@@ -210,6 +244,17 @@ dyson_status dyson_solve(dyson_plan* plan, int K, const double* d_V,
                          const double* d_omega, const double* d_sigma,
                          double* d_G, void* stream, dyson_report* report);
 
+/* The host-to-host form of dyson_solve: h_V [N], h_omega [K], h_sigma [K][N]
+ * and the output h_G [K][N] are HOST arrays (same layouts).  The inputs are
+ * copied to a device staging block (allocated through the context's allocator
+ * and freed before the call returns) on `stream`, the solve runs there, and G
+ * is copied back before the call returns; report->t_total_ms includes the
+ * copies.  Errors as dyson_solve, plus DYSON_ENOMEM if the staging block
+ * (16 (2 K N + N) bytes) cannot be allocated; h_G is untouched on error. */
+dyson_status dyson_solve_host(dyson_plan* plan, int K, const double* h_V, const double* h_omega,
+                              const double* h_sigma, double* h_G, void* stream,
+                              dyson_report* report);
+
 /* The same hot path at complex energies z_k with Im z_k > 0 instead of the
  * Matsubara points i w_k: H_ii = z_k + mu - V_i - Sigma_i(z_k) (eq. (1)
  * continued off the imaginary axis, e.g. z_k = w_k + i eta on the real
@@ -219,9 +264,15 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
                            const double* d_sigma, double* d_G, void* stream,
                            dyson_report* report);
 
-/* Measured choice of the tile shape: for each candidate leaf edge (8, 12, 16
- * on chains and squares; 4, 5, 6 on cubes; periodic axes keep only edges that
- * divide them) and level-stream count (1, 3, 4), a plan solves the probe inputs
+/* Candidates of dyson_autotune (initialiser lists). */
+#define DYSON_AUTOTUNE_EDGES_2D {8, 12, 16}
+#define DYSON_AUTOTUNE_EDGES_3D {4, 5, 6}
+#define DYSON_AUTOTUNE_LEVEL_STREAMS {1, 3, 4}
+
+/* Measured choice of the tile shape: for each candidate leaf edge
+ * (DYSON_AUTOTUNE_EDGES_2D on chains and squares, DYSON_AUTOTUNE_EDGES_3D on
+ * cubes; periodic axes keep only edges that divide them) and level-stream
+ * count (DYSON_AUTOTUNE_LEVEL_STREAMS), a plan solves the probe inputs
  * (K frequencies, device pointers as in dyson_solve) once after its
  * workspace is allocated; the fastest wins.  *best = base (NULL: defaults)
  * with leaf_edge and level_streams set; *rate = its site*freq/s.  The probe

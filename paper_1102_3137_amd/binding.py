@@ -38,7 +38,9 @@ class Opts(C.Structure):
     _fields_ = [("leaf_edge", C.c_int), ("partition", C.c_int), ("precision", C.c_int),
                 ("max_rank", C.c_int), ("extra_steps", C.c_int), ("max_inner_iters", C.c_int),
                 ("inner_tol", C.c_double), ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
-                ("profile", C.c_int), ("level_streams", C.c_int), ("check_sites", C.c_int)]
+                ("profile", C.c_int), ("level_streams", C.c_int), ("check_sites", C.c_int),
+                ("fault_step", C.c_int), ("fault_attempts", C.c_int),
+                ("breakdown_tol", C.c_double)]
 
 
 class Report(C.Structure):
@@ -47,7 +49,8 @@ class Report(C.Structure):
                 ("inner_iters_max", C.c_int), ("restarts", C.c_int), ("truncated", C.c_int),
                 ("kern_ms", C.c_double * 4), ("kern_launches", C.c_longlong * 4),
                 ("kern_bytes", C.c_double * 4), ("t_queue_ms", C.c_double),
-                ("batches", C.c_int), ("hbm_bytes", C.c_size_t), ("est_rel_err", C.c_double)]
+                ("batches", C.c_int), ("hbm_bytes", C.c_size_t), ("est_rel_err", C.c_double),
+                ("capped_items", C.c_int)]
 
     def as_dict(self):
         return {"t_total_ms": self.t_total_ms, "levels": self.levels,
@@ -57,7 +60,7 @@ class Report(C.Structure):
                 "kern_ms": list(self.kern_ms), "kern_launches": list(self.kern_launches),
                 "kern_bytes": list(self.kern_bytes), "t_queue_ms": self.t_queue_ms,
                 "batches": self.batches, "hbm_bytes": int(self.hbm_bytes),
-                "est_rel_err": self.est_rel_err}
+                "est_rel_err": self.est_rel_err, "capped_items": self.capped_items}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -86,9 +89,11 @@ SIGNATURES = [
     ("dyson_plan_destroy", C.c_int, [_P]),
     ("dyson_plan_get_info", C.c_int, [_P, C.POINTER(PlanInfo)]),
     ("dyson_plan_get_maps", C.c_int, [_P, _I, _I, _I]),
+    ("dyson_plan_get_domains", C.c_int, [_P, C.c_int, _I, _I]),
     ("dyson_footprint", C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     ("dyson_solve", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_solve_host", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_assemble", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
@@ -172,6 +177,15 @@ def dyson_plan_get_maps(plan, n_sites: int):
     return depth, is_sep, tile
 
 
+def dyson_plan_get_domains(plan, level: int, n_nodes: int):
+    import numpy as np
+    m = np.zeros(n_nodes, np.int32)
+    cap = np.zeros(n_nodes, np.int32)
+    _check(load_library().dyson_plan_get_domains(plan, level, m.ctypes.data_as(_I),
+                                                 cap.ctypes.data_as(_I)))
+    return m, cap
+
+
 def dyson_footprint(plan, K: int) -> int:
     b = C.c_size_t()
     _check(load_library().dyson_footprint(plan, K, C.byref(b)))
@@ -181,6 +195,12 @@ def dyson_footprint(plan, K: int) -> int:
 def dyson_solve(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream, report: Report | None = None):
     _check(load_library().dyson_solve(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
                                       C.byref(report) if report is not None else None))
+
+
+def dyson_solve_host(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                     report: Report | None = None):
+    _check(load_library().dyson_solve_host(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                                           C.byref(report) if report is not None else None))
 
 
 def dyson_solve_z(plan, K, V_ptr, z_ptr, sigma_ptr, G_ptr, stream, report: Report | None = None):
@@ -259,7 +279,7 @@ class Plan:
                  precision=PREC_FP64, max_rank=0, extra_steps=10, max_inner_iters=2000,
                  inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
                  ctx: "Context | None" = None, level_streams=4, periodic=None,
-                 check_sites=2):
+                 check_sites=2, fault_step=0, fault_attempts=0, breakdown_tol=1e-4):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
@@ -270,7 +290,8 @@ class Plan:
         lat.t, lat.mu = float(t), float(mu)
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
                  inner_tol, lanczos_tol, seed, int(profile), int(level_streams),
-                 int(check_sites) if check_sites else -1)
+                 int(check_sites) if check_sites else -1, int(fault_step), int(fault_attempts),
+                 float(breakdown_tol))
         self.dims = dims
         self.n_sites = 1
         for x in dims:
@@ -306,6 +327,26 @@ class Plan:
 
     def footprint(self, K):
         return dyson_footprint(self.plan, K)
+
+    def domains(self, level):
+        """(m, step cap) of every correction domain of the level."""
+        return dyson_plan_get_domains(self.plan, level, self.info.n_nodes[level])
+
+    def solve_host(self, V, omega, sigma, G=None, report=False):
+        """Host-to-host solve: numpy arrays in (V float64 [N], omega float64 [K],
+        sigma complex128 [K, N]), numpy G complex128 [K, N] out."""
+        import numpy as np
+        V = np.ascontiguousarray(V, np.float64)
+        omega = np.ascontiguousarray(omega, np.float64)
+        sigma = np.ascontiguousarray(sigma, np.complex128)
+        K = int(omega.shape[0])
+        if G is None:
+            G = np.empty((K, self.n_sites), np.complex128)
+        assert G.dtype == np.complex128 and G.flags.c_contiguous
+        cp = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
+        rep = Report()
+        dyson_solve_host(self.plan, K, cp(V), cp(omega), cp(sigma), cp(G), _stream(), rep)
+        return (G, rep.as_dict()) if report else G
 
     @staticmethod
     def _c(x):

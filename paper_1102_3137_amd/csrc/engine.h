@@ -21,6 +21,7 @@
 namespace dyson {
 
 void set_error(const std::string& msg);
+extern const double kMinImMixed16;  // smallest Im H_ii of a DYSON_PREC_MIXED16 solve
 const std::string& get_error();
 
 struct DevLevel {
@@ -61,7 +62,7 @@ struct Work {
   double* partial = nullptr;
   double *hpart = nullptr, *h = nullptr;
   CocgState cst{};
-  int *lz_stopped = nullptr, *lz_steps = nullptr, *lz_reorth = nullptr;
+  int *lz_stopped = nullptr, *lz_steps = nullptr, *lz_reorth = nullptr, *lz_armed = nullptr;
   double* Dl = nullptr;  // diagonal correction of the level being run
   double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
          *lz_scal = nullptr;

@@ -78,6 +78,8 @@ struct LzArgs {
   unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (CGS update,
                              // CGS products) booked by each item's lead block, or null
   int* reorth;      // [n_items] 1 if the second Gram-Schmidt pass runs for the item
+  int* armed;       // [n_items] 1 after a step whose residual passed the L2 stop test:
+                    // the next step confirms exhaustion (|X q| at the noise level)
 };
 
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
@@ -88,8 +90,10 @@ void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const
                      int zmode, const double* sigma, double* d, hipStream_t s);
 // eq. (1) input checks, OR-ed into *flag: 1 non-finite V, 2 Im z_k <= 0 or
 // non-finite z_k, 4 non-finite Sigma, 8 Im(z_k - Sigma_i) <= 0.
+// With min_im > 0 also 16: Im(z_k - Sigma_i) < min_im (complex32 factors need
+// their entries, bounded by 1 / min Im H_ii, inside the FP16 range).
 void launch_validate(int N, int K, const double* V, const double* omega, int zmode,
-                     const double* sigma, int* flag, hipStream_t s);
+                     const double* sigma, double min_im, int* flag, hipStream_t s);
 // Tile block factors of graph g (complex128 / complex64 / complex32 storage).
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s);
@@ -125,8 +129,9 @@ void launch_cgs_decide(const LzArgs& a, int K, const int* tlo, const int* thi, i
                        double eta2, hipStream_t s);
 void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s);
 void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s);
+// force (op 2): declare every open item broken down at this step (test hook)
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
-                       int op, int j, double tol, double brk, hipStream_t s);
+                       int op, int j, double tol, double brk, int force, hipStream_t s);
 void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s);
 void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s);
 // Sampled check: b = e_pos in every frequency row; err = max(err, max_k |x - g| / |x|) at pos.

@@ -60,7 +60,8 @@ __global__ void k_assemble(TileGeom G, int K, double mu, const double* __restric
 // Input checks of eq. (1); Im(i w_k - Sigma_i) > 0 keeps Im H positive
 // definite, which the pivot-free factorizations rely on.
 __global__ void k_validate(int N, const double* __restrict__ V, const double* __restrict__ omega,
-                           int zmode, const double* __restrict__ sigma, int* __restrict__ flag) {
+                           int zmode, const double* __restrict__ sigma, double min_im,
+                           int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (i >= N) return;
@@ -71,6 +72,7 @@ __global__ void k_validate(int N, const double* __restrict__ V, const double* __
   const cd sg = ld(sigma, (size_t)k * N + i);
   if (!isfinite(sg.x) || !isfinite(sg.y)) f |= 4;
   else if (!(z.y - sg.y > 0.0)) f |= 8;
+  else if (z.y - sg.y < min_im) f |= 16;
   if (f) atomicOr(flag, f);
 }
 
@@ -546,11 +548,20 @@ __global__ void k_lz_next(LzArgs a, const double* __restrict__ r, double* __rest
 
 // Per-item scalar steps of the Lanczos recurrence.
 //   op 0: start   scal = 1/sqrt(q^T q)
-//   op 1: alpha   alpha = q^T u, unorm2 = |u|^2
+//   op 1: alpha   alpha = q^T u, unorm2 = |u|^2; an armed item whose new
+//                 |u| = |X q_j| is at the noise level stops here (exhausted)
 //   op 2: norms   stop test, beta_{j+1} = principal sqrt(r^T r)
+//
+// Stopping (Sec. II.C: the coefficients vanish once the Krylov space of X is
+// exhausted).  A residual that passes the L2 test |r| <= tol |u| may also be
+// a transient dip; the item is then armed and runs one more step: at
+// exhaustion q_{j+1} is bilinear-orthogonal to a basis that spans the range
+// of X, so |X q_{j+1}| is at the noise level of the inner solves, while a
+// dip leaves a direction with |X q_{j+1}| comparable to |X|.  The step count
+// and the diagonal keep only the steps before the confirming one.
 __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
                              const int* __restrict__ thi, const int* __restrict__ mcap, int op,
-                             int j, double tol, double brk) {
+                             int j, double tol, double brk, int force) {
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= K * a.n_nodes) return;
   const int k = item / a.n_nodes, node = item % a.n_nodes;
@@ -582,9 +593,18 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     st(a.beta, item, cmk(0.0, 0.0));
     a.steps[item] = 0;
     a.umax2[item] = 0.0;
+    a.armed[item] = 0;
     return;
   }
   if (op == 1) {
+    if (a.armed[item]) {
+      // the confirming step: |u|^2 <= tol |X|^2 (|u| <= sqrt(tol) max|u|)
+      if (s1.x <= tol * a.umax2[item]) {
+        a.stopped[item] = 1;  // exhausted; this step contributes nothing
+        return;
+      }
+      a.armed[item] = 0;  // a transient dip: carry on
+    }
     st(a.alpha, item, s0);
     a.unorm2[item] = s1.x;
     a.umax2[item] = fmax(a.umax2[item], s1.x);
@@ -592,21 +612,32 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
   }
   const int steps = j + 1;
   a.steps[item] = steps;
-  // exhausted when the new residual is at the noise level of this step's
-  // X-matvec, or (backstop) far below the largest |u| seen, an estimate of |X|
+  if (force) {
+    a.stopped[item] = 3;  // test hook: breakdown declared at this step
+    return;
+  }
+  // the residual far below the largest |u| seen (an estimate of |X|), or a
+  // zero X-matvec: exhausted without doubt; the L2 test arms the item
   const double rn = sqrt(s0.x), un = sqrt(a.unorm2[item]);
-  if (rn <= tol * un || rn <= 1e-3 * tol * sqrt(a.umax2[item]) || un == 0.0) {
+  if (rn <= 1e-3 * tol * sqrt(a.umax2[item]) || un == 0.0) {
     a.stopped[item] = 1;  // the Krylov space of X is exhausted: T_j is complete
+    return;
+  }
+  const bool l2 = rn <= tol * un;
+  const bool broken = sqrt(cabs2(s1)) <= brk * s0.x;
+  if (l2 && (steps >= mcap[node] || broken)) {
+    a.stopped[item] = 1;  // no room (or no usable vector) to confirm: the L2 test decides
     return;
   }
   if (steps >= mcap[node]) {
     a.stopped[item] = 2;  // step cap (rank cap or m + extra)
     return;
   }
-  if (sqrt(cabs2(s1)) <= brk * s0.x) {
+  if (broken) {
     a.stopped[item] = 3;  // serious breakdown of the bilinear form: redo the item
     return;
   }
+  if (l2) a.armed[item] = 1;
   st(a.beta, item, csqrt_p(s1));
 }
 
@@ -683,9 +714,9 @@ void launch_assemble(const TileGeom& G, int K, double mu, const double* V, const
   k_assemble<<<grid, 256, 0, s>>>(G, K, mu, V, omega, zmode, sigma, d);
 }
 void launch_validate(int N, int K, const double* V, const double* omega, int zmode,
-                     const double* sigma, int* flag, hipStream_t s) {
+                     const double* sigma, double min_im, int* flag, hipStream_t s) {
   dim3 grid((unsigned)((N + 255) / 256), K);
-  k_validate<<<grid, 256, 0, s>>>(N, V, omega, zmode, sigma, flag);
+  k_validate<<<grid, 256, 0, s>>>(N, V, omega, zmode, sigma, min_im, flag);
 }
 void launch_factor(const TileGeom& G, int K, int g, const int* tile_node, const double* d,
                    void* fac, bool fp32, bool fp16, hipStream_t s) {
@@ -753,9 +784,9 @@ void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStre
   k_lz_next<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r, qn);
 }
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
-                       int op, int j, double tol, double brk, hipStream_t s) {
+                       int op, int j, double tol, double brk, int force, hipStream_t s) {
   int n = K * a.n_nodes;
-  k_lz_scalars<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, mcap, op, j, tol, brk);
+  k_lz_scalars<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, mcap, op, j, tol, brk, force);
 }
 void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s) {
   k_lz_clear_bad<<<tiles_grid(a.G, K), 256, 0, s>>>(a, D);

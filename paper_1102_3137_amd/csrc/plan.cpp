@@ -25,6 +25,7 @@ dyson_opts default_opts() {
   o.profile = 0;
   o.level_streams = 4;
   o.check_sites = 2;
+  o.breakdown_tol = 1e-4;
   return o;
 }
 
@@ -43,6 +44,9 @@ dyson_opts merge_opts(const dyson_opts* u) {
   o.profile = u->profile;
   if (u->level_streams) o.level_streams = u->level_streams;
   if (u->check_sites) o.check_sites = u->check_sites < 0 ? 0 : u->check_sites;
+  o.fault_step = u->fault_step;
+  o.fault_attempts = u->fault_attempts;
+  if (u->breakdown_tol > 0) o.breakdown_tol = u->breakdown_tol;
   return o;
 }
 
@@ -77,6 +81,10 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
     return "max_inner_iters must be in [1, 1000000] (0 selects the default)";
   if (opts.level_streams < 1 || opts.level_streams > 8) return "level_streams must be in [1, 8]";
   if (opts.check_sites < 0 || opts.check_sites > 2) return "check_sites must be in [-1, 2]";
+  if (opts.fault_step < 0 || opts.fault_attempts < 0 || opts.fault_attempts > 3)
+    return "fault_step must be >= 0 and fault_attempts in [0, 3]";
+  if (!(opts.breakdown_tol > 0.0 && opts.breakdown_tol < 1.0))
+    return "breakdown_tol must be in (0, 1)";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
   if (n > (1LL << 28)) return "lattice too large";
 

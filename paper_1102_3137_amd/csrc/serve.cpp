@@ -434,8 +434,12 @@ dyson_status start_server(dyson_ctx* c, std::shared_ptr<Server>* out) {
   return DYSON_OK;
 }
 
+const char* kMixed16Msg =
+    "DYSON_PREC_MIXED16 needs Im(z_k - Sigma_i) >= 2^-14: its FP16 factor entries reach "
+    "1 / min Im H_ii; use DYSON_PREC_MIXED or DYSON_PREC_FP64";
+
 dyson_status validate_host(int N, int K, const double* V, const double* om, int zmode,
-                           const double* sg) {
+                           const double* sg, double min_im) {
   for (int i = 0; i < N; ++i)
     if (!std::isfinite(V[i])) return fail(DYSON_EINVAL, "V contains a non-finite value");
   for (int k = 0; k < K; ++k) {
@@ -448,13 +452,14 @@ dyson_status validate_host(int N, int K, const double* V, const double* om, int 
         return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
       if (!(zi - im > 0))
         return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
+      if (zi - im < min_im) return fail(DYSON_EUNSUPPORTED, kMixed16Msg);
     }
   }
   return DYSON_OK;
 }
 
 dyson_status validate_device(Server& srv, int N, int K, const double* V, const double* om,
-                             int zmode, const double* sg) {
+                             int zmode, const double* sg, double min_im) {
   std::lock_guard<std::mutex> g(srv.vm);
   if (hipSetDevice(srv.device) != hipSuccess ||
       hipMemsetAsync(srv.vflag, 0, sizeof(int), srv.vstream) != hipSuccess)
@@ -463,7 +468,7 @@ dyson_status validate_device(Server& srv, int N, int K, const double* V, const d
   for (int k0 = 0; k0 < K; k0 += 65535) {
     const int kn = std::min(K - k0, 65535);
     launch_validate(N, kn, V, om + (size_t)k0 * (zmode ? 2 : 1), zmode,
-                    sg + (size_t)k0 * N * 2, srv.vflag, srv.vstream);
+                    sg + (size_t)k0 * N * 2, min_im, srv.vflag, srv.vstream);
   }
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(srv.hflag, srv.vflag, sizeof(int), hipMemcpyDeviceToHost, srv.vstream) !=
@@ -475,6 +480,7 @@ dyson_status validate_device(Server& srv, int N, int K, const double* V, const d
   if (f & 2) return fail(DYSON_EINVAL, "frequencies must be finite with w_k > 0 (Im z_k > 0)");
   if (f & 4) return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
   if (f & 8) return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
+  if (f & 16) return fail(DYSON_EUNSUPPORTED, kMixed16Msg);
   return DYSON_OK;
 }
 
@@ -493,6 +499,7 @@ dyson_status submit(dyson_plan* plan, int K, const double* V, const double* omeg
   dyson_status s0 = start_server(plan->ctx, &srv);
   if (s0 != DYSON_OK) return s0;
   const int N = plan->hp.N;
+  const double min_im = plan->hp.opts.precision == DYSON_PREC_MIXED16 ? kMinImMixed16 : 0.0;
   auto r = std::make_shared<ReqState>();
   r->plan = plan;
   r->K = K;
@@ -500,13 +507,13 @@ dyson_status submit(dyson_plan* plan, int K, const double* V, const double* omeg
   r->zmode = zmode;
   r->G = G;
   if (mem == DYSON_MEM_HOST) {
-    dyson_status sv = validate_host(N, K, V, omega, zmode, sigma);
+    dyson_status sv = validate_host(N, K, V, omega, zmode, sigma, min_im);
     if (sv != DYSON_OK) return sv;
     r->hV.assign(V, V + N);
     r->hom.assign(omega, omega + (size_t)K * (zmode ? 2 : 1));
     r->hsig.assign(sigma, sigma + (size_t)2 * K * N);
   } else {
-    dyson_status sv = validate_device(*srv, N, K, V, omega, zmode, sigma);
+    dyson_status sv = validate_device(*srv, N, K, V, omega, zmode, sigma, min_im);
     if (sv != DYSON_OK) return sv;
     r->V = V;
     r->omega = omega;

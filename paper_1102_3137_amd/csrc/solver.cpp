@@ -84,6 +84,18 @@ namespace {
 // per-(tile, frequency) launches.
 constexpr int kMaxFreqs = 65535;
 
+}  // namespace
+
+namespace dyson {
+// Smallest Im H_ii a complex32 (FP16-pair) factorization accepts.  Every
+// principal submatrix A of H has Im A >= min_i Im H_ii > 0 (Im H is diagonal
+// and positive), so |A^{-1}| <= 1 / min_i Im H_ii bounds the entries of the
+// slice inverses; 2^-14 keeps them below 16384, a quarter of the FP16 maximum.
+const double kMinImMixed16 = 1.0 / 16384.0;
+}  // namespace dyson
+
+namespace {
+
 // Lanczos step cap of a domain with interface size m: the paper allows 5-10
 // steps beyond m for m ~ 100; bilinear Lanczos in floating point needs more
 // as m grows (m + 11 observed at m = 128), so the allowance scales as m/8.
@@ -122,7 +134,7 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->alph, ni * 16},
       {(void**)&w->partS, (size_t)K * P.T * 16},
       {(void**)&w->lz_stopped, ni * 4}, {(void**)&w->lz_steps, ni * 4},
-      {(void**)&w->lz_reorth, ni * 4},
+      {(void**)&w->lz_reorth, ni * 4}, {(void**)&w->lz_armed, ni * 4},
       {(void**)&w->lz_alpha, ni * 16},  {(void**)&w->lz_beta, ni * 16},
       {(void**)&w->lz_unorm2, ni * 8},  {(void**)&w->lz_umax2, ni * 8},
       {(void**)&w->lz_scal, ni * 16},   {(void**)&w->d_count, 16},
@@ -467,6 +479,7 @@ struct Run {
     a.n_items = K * p->lv[level].n;
     a.wctr = w->prof.on ? w->d_wprof + 2 * (size_t)K * p->nmax : nullptr;
     a.reorth = w->lz_reorth;
+    a.armed = w->lz_armed;
     return a;
   }
 
@@ -516,7 +529,10 @@ struct Run {
     HIPC(hipMemsetAsync(w->Dl, 0, V * sizeof(double), s));
     LzArgs a = lz_args(level);
     const int n_items = K * L.n;
-    const double brk = 1e-6;  // |r^T r| <= brk |r|^2 would give |q| >= 1e3: redo the item
+    // |r^T r| <= brk |r|^2: redo the item; each further attempt accepts a
+    // 100x smaller ratio, so a strict threshold buys accuracy on the first
+    // attempt without failing an item whose fresh starts all come close
+    double brk = HP.opts.breakdown_tol;
     int kmax = 0;
     for (int m : HP.levels[level].m) kmax = std::max(kmax, step_cap(m, HP.opts));
     kmax = std::min(kmax, w->kq);
@@ -524,7 +540,7 @@ struct Run {
     for (int attempt = 0; attempt < 3; ++attempt) {
       // start vector, normalized in the bilinear "norm"
       launch_lz_random(a, K, Qj(0), (uint64_t)attempt, s);
-      launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 0, 0, HP.opts.lanczos_tol, brk, s);
+      launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 0, 0, HP.opts.lanczos_tol, brk, 0, s);
       launch_lz_scale(a, K, Qj(0), s);
       HIPC(hipGetLastError());
       const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
@@ -539,12 +555,14 @@ struct Run {
         }
         const double* q = Qj(j);
         CHECKED(xmatvec(level, q, w->xH));
+        if (w->pending != DYSON_OK) break;  // an inner solve failed: the level cannot finish
         launch_lz_alpha(a, K, q, w->xH, s);
-        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 1, j, HP.opts.lanczos_tol, brk, s);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 1, j, HP.opts.lanczos_tol, brk, 0, s);
         launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, w->xH, w->R, w->Dl, s);
         cgs2(a, L, j + 1);
         launch_lz_norms(a, K, w->R, s);
-        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, s);
+        const int force = (HP.opts.fault_step == j + 1 && attempt < HP.opts.fault_attempts);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.mcap, 2, j, HP.opts.lanczos_tol, brk, force, s);
         if (j + 1 < w->kq) launch_lz_next(a, K, w->R, Qj(j + 1), s);
         HIPC(hipGetLastError());
       }
@@ -562,13 +580,14 @@ struct Run {
         std::fprintf(stderr, "[dyson] level %d attempt %d: stop codes open=%d exhausted=%d cap=%d breakdown=%d\n",
                      level, attempt, hist[0], hist[1], hist[2], hist[3]);
       }
-      if (bad == 0) break;
+      if (bad == 0 || w->pending != DYSON_OK) break;
       if (attempt == 2) {
         w->pending = DYSON_EBREAKDOWN;
         g_err = "Lanczos breakdown persisted after restarts";
         break;
       }
       w->stat_restarts += bad;
+      brk *= 1e-2;
       launch_lz_reopen(a, K, w->Dl, s);
       HIPC(hipGetLastError());
     }
@@ -607,7 +626,8 @@ dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int 
     if (sl[j].K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
     if (!sl[j].V || !sl[j].omega || !sl[j].sigma || !sl[j].G)
       return fail(DYSON_EINVAL, "null input or output pointer");
-    launch_validate(N, sl[j].K, sl[j].V, sl[j].omega, sl[j].zmode, sl[j].sigma, w->d_flag, s);
+    launch_validate(N, sl[j].K, sl[j].V, sl[j].omega, sl[j].zmode, sl[j].sigma,
+                    p->hp.opts.precision == DYSON_PREC_MIXED16 ? kMinImMixed16 : 0.0, w->d_flag, s);
   }
   HIPC(hipGetLastError());
   HIPC(hipMemcpyAsync(w->h_count, w->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -617,6 +637,10 @@ dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int 
   if (f & 2) return fail(DYSON_EINVAL, "frequencies must be finite with w_k > 0 (Im z_k > 0)");
   if (f & 4) return fail(DYSON_EINVAL, "Sigma contains a non-finite value");
   if (f & 8) return fail(DYSON_EINVAL, "Im(z_k - Sigma_i) must be > 0 (causal self-energy)");
+  if (f & 16)
+    return fail(DYSON_EUNSUPPORTED,
+                "DYSON_PREC_MIXED16 needs Im(z_k - Sigma_i) >= 2^-14: its FP16 factor entries "
+                "reach 1 / min Im H_ii; use DYSON_PREC_MIXED or DYSON_PREC_FP64");
   return DYSON_OK;
 }
 
@@ -769,6 +793,7 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
     rep->inner_iters_max = w->stat_inner_max;
     rep->restarts = w->stat_restarts;
     rep->truncated = w->stat_capped > 0 ? 1 : 0;
+    rep->capped_items = w->stat_capped;
     rep->batches = 1;
     rep->hbm_bytes = w->bytes;
     rep->est_rel_err = est;
@@ -963,6 +988,18 @@ dyson_status dyson_plan_get_maps(const dyson_plan* p, int* h_depth, int* h_is_se
   return DYSON_OK;
 }
 
+dyson_status dyson_plan_get_domains(const dyson_plan* p, int level, int* h_m, int* h_cap) {
+  if (!p) return fail(DYSON_EINVAL, "null plan");
+  const HostPlan& P = p->hp;
+  if (level < 0 || level >= (int)P.levels.size()) return fail(DYSON_EINVAL, "bad level");
+  const LevelTable& L = P.levels[level];
+  for (int i = 0; i < L.n_nodes; ++i) {
+    if (h_m) h_m[i] = L.m[i];
+    if (h_cap) h_cap[i] = step_cap(L.m[i], P.opts);
+  }
+  return DYSON_OK;
+}
+
 dyson_status dyson_footprint(const dyson_plan* p, int K, size_t* bytes) {
   if (!p || !bytes || K < 1) return fail(DYSON_EINVAL, "bad argument");
   *bytes = work_bytes(p, K);
@@ -1046,14 +1083,58 @@ dyson_status dyson_solve(dyson_plan* p, int K, const double* d_V, const double* 
   return run_solve(p, w, &sl, 1, s, rep, nullptr);
 }
 
+dyson_status dyson_solve_host(dyson_plan* p, int K, const double* h_V, const double* h_omega,
+                              const double* h_sigma, double* h_G, void* stream,
+                              dyson_report* rep) {
+  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
+  if (K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "K must be in [1, 65535]");
+  if (!h_V || !h_omega || !h_sigma || !h_G) return fail(DYSON_EINVAL, "null input or output pointer");
+  hipStream_t s = (hipStream_t)stream;
+  HIPC(hipSetDevice(p->ctx->device));
+  const size_t N = (size_t)p->hp.N;
+  const size_t bV = N * 8, bOm = (size_t)K * 8, bSig = (size_t)K * N * 16;
+  // one staging block for the inputs and G, freed before returning
+  char* buf = (char*)dev_alloc(p->ctx, bV + bOm + 2 * bSig + 1024, s);
+  if (!buf) return fail(DYSON_ENOMEM, "device staging of the host arrays failed");
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  double* dV = (double*)buf;
+  double* dOm = (double*)(buf + al(bV));
+  double* dSig = (double*)(buf + al(bV) + al(bOm));
+  double* dG = (double*)(buf + al(bV) + al(bOm) + al(bSig));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto go = [&]() -> dyson_status {
+    HIPC(hipMemcpyAsync(dV, h_V, bV, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(dOm, h_omega, bOm, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(dSig, h_sigma, bSig, hipMemcpyHostToDevice, s));
+    Work* w = &p->main;
+    CHECKED(ensure_work(p, w, K, s));
+    Slice sl{K, dV, dOm, dSig, dG, 0};
+    CHECKED(validate_slices(p, w, &sl, 1, s));
+    CHECKED(run_solve(p, w, &sl, 1, s, rep, nullptr));
+    HIPC(hipMemcpyAsync(h_G, dG, bSig, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (rep)  // host to host: the copies are part of the call's time
+      rep->t_total_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return DYSON_OK;
+  };
+  const dyson_status st = go();
+  (void)hipStreamSynchronize(s);
+  const std::string msg = g_err;
+  dev_free(p->ctx, buf, s);
+  g_err = msg;
+  return st;
+}
+
 dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyson_opts* base,
                             int K, const double* d_V, const double* d_omega,
                             const double* d_sigma, dyson_opts* best, double* rate) {
   if (!ctx || !lat || !best || K < 1 || K > kMaxFreqs) return fail(DYSON_EINVAL, "bad argument");
   if (!d_V || !d_omega || !d_sigma) return fail(DYSON_EINVAL, "null input pointer");
   const dyson_opts b0 = merge_opts(base);
-  std::vector<int> edges = (lat->dim == 3) ? std::vector<int>{4, 5, 6} : std::vector<int>{8, 12, 16};
-  const int streams[3] = {1, 3, 4};
+  std::vector<int> edges = (lat->dim == 3) ? std::vector<int>DYSON_AUTOTUNE_EDGES_3D
+                                            : std::vector<int>DYSON_AUTOTUNE_EDGES_2D;
+  const std::vector<int> streams = DYSON_AUTOTUNE_LEVEL_STREAMS;
   long long n = 1;
   for (int a = 0; a < 3; ++a) n *= std::max(1, lat->L[a]);
   HIPC(hipSetDevice(ctx->device));

@@ -53,6 +53,42 @@ def test_open_uniform_closed_form(dims):
     assert oracle.rel_err(od.diag_inv_rgf(dims, d, -1.0), ref) < 1e-13
 
 
+@pytest.mark.parametrize("dims", [(9,), (6, 5), (4, 3, 5)])
+@pytest.mark.parametrize("c", [0.7, -1.3])
+def test_potential_enters_with_minus_sign(dims, c):
+    """eq. (1) subtracts V_i: a uniform potential V_i = c with Sigma = 0 is
+    the uniform open lattice at the shifted energy z = i w + mu - c, whose
+    sine-mode closed form is independent of the assembly.  A planted +V
+    (the closed form at i w + mu + c) fails the same comparison."""
+    n = int(np.prod(dims))
+    om, mu, t = np.array([0.37]), 0.4, -1.0
+    V = np.full(n, c)
+    sig = np.zeros((1, n), complex)
+    d = oracle.assemble_diag(V, om, sig, mu)[0]
+    ref = oracle.closed_form_open_uniform(dims, 1j * om[0] + mu - c, t)
+    assert oracle.rel_err(od.diag_inv_dense(dims, d, t), ref) < 1e-13
+    assert oracle.rel_err(od.diag_inv_rgf(dims, d, t), ref) < 1e-13
+    planted = (1j * om[0] + mu) + V - sig[0]
+    assert oracle.rel_err(od.diag_inv_dense(dims, planted, t), ref) > 1e-2
+
+
+def test_site_potential_shifts_only_its_site_at_high_frequency():
+    """A potential on one site: to first order in 1/|d| the change of G_jj is
+    -(1/(z - V_j) - 1/z) on that site only, with the sign of -V_j fixed by
+    eq. (1) (z = i w + mu, uniform elsewhere, t small against |z|)."""
+    dims, n = (5, 4), 20
+    om, mu, t, j, vj = np.array([30.0]), 0.2, -0.05, 7, 2.5
+    V = np.zeros(n)
+    V[j] = vj
+    d = oracle.assemble_diag(V, om, np.zeros((1, n), complex), mu)[0]
+    G = od.diag_inv_dense(dims, d, t)
+    z = 1j * om[0] + mu
+    assert abs(G[j] - 1.0 / (z - vj)) < 10 * t * t / abs(z) ** 3
+    assert abs(G[j] - 1.0 / (z + vj)) > 100 * t * t / abs(z) ** 3
+    others = np.delete(np.arange(n), j)
+    assert np.max(np.abs(G[others] - 1.0 / z)) < 10 * t * t / abs(z) ** 3
+
+
 @pytest.mark.parametrize("dims,per", [((6, 5), (1, 0)), ((5, 7), (0, 1)), ((4, 3, 5), (0, 1, 1)),
                                       ((3, 4, 3), (1, 0, 1)), ((8,), (1,))])
 def test_mixed_boundary_closed_form(dims, per):
