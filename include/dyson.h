@@ -244,6 +244,27 @@ dyson_status dyson_solve(dyson_plan* plan, int K, const double* d_V,
                          const double* d_omega, const double* d_sigma,
                          double* d_G, void* stream, dyson_report* report);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): dyson_solve with no
+ * allocation at all.  The workspace is carved from a fixed device array of
+ * dyson_noalloc_max_bytes() bytes (256 MiB) that each device holds from the
+ * first dyson_create on it until the process ends; inputs and output are the
+ * caller's device buffers, as in dyson_solve.  The correction levels run one
+ * after another on `stream` (the result equals dyson_solve with
+ * level_streams = 1 bit for bit) and no profiling events are recorded.
+ * Returns DYSON_EINVAL, before touching the device, when the plan's workspace
+ * for K frequencies (dyson_noalloc_bytes) exceeds the array.  Every call on a
+ * device uses the same array and leaves its contents behind: calls that
+ * overlap on one device (threads, streams, plans) race and must be serialised
+ * by the caller. */
+dyson_status dyson_solve_noalloc(dyson_plan* plan, int K, const double* d_V,
+                                 const double* d_omega, const double* d_sigma, double* d_G,
+                                 void* stream, dyson_report* report);
+/* Scratch bytes dyson_solve_noalloc needs for K frequencies of the plan. */
+dyson_status dyson_noalloc_bytes(const dyson_plan* plan, int K, size_t* bytes);
+/* Size of the per-device scratch array. */
+size_t dyson_noalloc_max_bytes(void);
+
 /* The host-to-host form of dyson_solve: h_V [N], h_omega [K], h_sigma [K][N]
  * and the output h_G [K][N] are HOST arrays (same layouts).  The inputs are
  * copied to a device staging block (allocated through the context's allocator

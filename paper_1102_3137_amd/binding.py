@@ -94,6 +94,9 @@ SIGNATURES = [
     ("dyson_solve", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_host", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_solve_noalloc", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_noalloc_bytes", C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
+    ("dyson_noalloc_max_bytes", C.c_size_t, []),
     ("dyson_assemble", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     ("dyson_leaf_diag", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dyson_xmatvec", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
@@ -201,6 +204,22 @@ def dyson_solve_host(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
                      report: Report | None = None):
     _check(load_library().dyson_solve_host(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
                                            C.byref(report) if report is not None else None))
+
+
+def dyson_solve_noalloc(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                        report: Report | None = None):
+    _check(load_library().dyson_solve_noalloc(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                                              C.byref(report) if report is not None else None))
+
+
+def dyson_noalloc_bytes(plan, K: int) -> int:
+    b = C.c_size_t()
+    _check(load_library().dyson_noalloc_bytes(plan, K, C.byref(b)))
+    return int(b.value)
+
+
+def dyson_noalloc_max_bytes() -> int:
+    return int(load_library().dyson_noalloc_max_bytes())
 
 
 def dyson_solve_z(plan, K, V_ptr, z_ptr, sigma_ptr, G_ptr, stream, report: Report | None = None):
@@ -367,6 +386,18 @@ class Plan:
         dyson_solve(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)), _ptr(self._c(sigma)),
                     _ptr(self._c(G)), _stream(), rep)
         return (G, rep.as_dict()) if report else G
+
+    def solve_noalloc(self, V, omega, sigma, G, report=False):
+        """dyson_solve_noalloc: the workspace comes from the device's fixed
+        scratch array; G (complex128 [K, N] on the GPU) is the caller's."""
+        K = int(omega.shape[0])
+        rep = Report()
+        dyson_solve_noalloc(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)),
+                            _ptr(self._c(sigma)), _ptr(self._c(G)), _stream(), rep)
+        return (G, rep.as_dict()) if report else G
+
+    def noalloc_bytes(self, K):
+        return dyson_noalloc_bytes(self.plan, K)
 
     def solve_z(self, V, z, sigma, G=None, report=False):
         """The solve at complex energies z (complex128 [K], Im z > 0)."""

@@ -1037,7 +1037,7 @@ void launch_prof_collect(unsigned long long* per_item, int n, int classes, int f
   k_prof_collect<<<1, 256, 0, s>>>(per_item, n, classes, first_class, tot);
 }
 void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
-  (void)hipMemsetAsync(open, 0, sizeof(int), s);
+  launch_zero(open, sizeof(int), s);
   if (L.n_items > 0) k_cocg_check<<<(unsigned)((L.n_items + 3) / 4), 256, 0, s>>>(L, it, open);
 }
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {

@@ -72,7 +72,12 @@ struct Work {
   double* partS = nullptr;  // inner solves: per-unit p^T A p
   double* stage_om = nullptr;  // [2*Kcap] staging of host-side frequencies
   std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
-  int* h_count = nullptr;   // pinned
+  int* h_count = nullptr;   // pinned (h_static for a carved Work)
+  // carved: the buffers are slices of a caller-provided region (the
+  // allocation-free entry point); nothing is freed, no profiling events are
+  // made and the correction levels run as one group on the call's stream
+  bool carved = false;
+  int h_static[4] = {0, 0, 0, 0};
   unsigned long long* d_prof = nullptr;
   unsigned long long* d_wprof = nullptr;  // [4][Kcap*nmax] per-item byte counts (profiling):
                                           // inner solves in [0,2), Lanczos in [2,4)
@@ -124,6 +129,7 @@ struct dyson_plan {
   int hstride = 1;
   std::vector<int> check_pos;  // tile positions of the sampled error check
   dyson::Work main;  // workspace of the blocking entry points
+  dyson::Work carved;  // slices of the device's scratch array (dyson_solve_noalloc)
   std::atomic<int> live_requests{0};
 };
 
@@ -147,6 +153,14 @@ std::vector<std::vector<int>> level_groups(const dyson_plan* p);
 
 // Device bytes a Work for K frequencies of the plan holds (with its groups).
 size_t work_bytes(const dyson_plan* p, int K);
+// Device bytes a carved Work (one level group) for K frequencies needs.
+size_t carved_bytes(const dyson_plan* p, int K);
+// Points every buffer of *w at consecutive 256-byte aligned slices of
+// [base, base + cap) for K frequencies; DYSON_EINVAL if they do not fit.
+dyson_status carve_work(const dyson_plan* p, Work* w, int K, char* base, size_t cap);
+// Allocation-free path (noalloc.hip): records the device address of the
+// device's scratch array; called once per device by dyson_create.
+dyson_status noalloc_init(int device);
 dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s);
 void free_work(Work* w, hipStream_t s);
 

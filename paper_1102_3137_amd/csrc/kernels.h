@@ -82,6 +82,8 @@ struct LzArgs {
                     // the next step confirms exhaustion (|X q| at the noise level)
 };
 
+// Zeroes `bytes` bytes (a multiple of 4) at device address p on stream s.
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fill_re,
                     hipStream_t s);
 void launch_from_tile(const TileGeom& G, int K, const double* tile, double* nat, hipStream_t s);

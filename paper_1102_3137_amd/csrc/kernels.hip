@@ -4,6 +4,8 @@
 // interleaved (re, im) pairs; all products are bilinear (no conjugation):
 // H is complex symmetric (Sec. I), and so are its blocks and inverses.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "devcommon.h"
@@ -660,6 +662,14 @@ __global__ void k_lz_reopen(LzArgs a, int n_items) {
   a.stopped[item] = (a.stopped[item] == 3) ? 0 : 4;
 }
 
+// Zero fill of n 4-byte words (vector stores; takes the place of a
+// runtime memset, so a stream of this library's work holds kernels only).
+__global__ void k_zero(uint32_t* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // b = e_pos in every frequency row (tile layout)
 __global__ void k_unit_vector(TileGeom G, int pos, double* __restrict__ b) {
   const size_t NP = (size_t)G.T * G.S;
@@ -737,6 +747,12 @@ void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64
   else k_factor_diag<36><<<tiles_grid(G, K), 256, 0, s>>>(G, d, fac64, gdiag);
 }
 
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;  // every buffer cleared here is a multiple of 4 bytes
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  k_zero<<<(unsigned)blocks, 256, 0, s>>>(reinterpret_cast<uint32_t*>(p), n);
+}
 void launch_count_open(const int* done, int n, int* out, hipStream_t s) {
   k_count_open<<<1, 256, 0, s>>>(done, n, out);
 }

@@ -461,9 +461,9 @@ dyson_status validate_host(int N, int K, const double* V, const double* om, int 
 dyson_status validate_device(Server& srv, int N, int K, const double* V, const double* om,
                              int zmode, const double* sg, double min_im) {
   std::lock_guard<std::mutex> g(srv.vm);
-  if (hipSetDevice(srv.device) != hipSuccess ||
-      hipMemsetAsync(srv.vflag, 0, sizeof(int), srv.vstream) != hipSuccess)
+  if (hipSetDevice(srv.device) != hipSuccess)
     return fail(DYSON_EDEVICE, "validation launch failed");
+  launch_zero(srv.vflag, sizeof(int), srv.vstream);
   // frequencies index the second grid dimension: at most 65535 per launch
   for (int k0 = 0; k0 < K; k0 += 65535) {
     const int kn = std::min(K - k0, 65535);

@@ -233,7 +233,38 @@ size_t work_bytes(const dyson_plan* p, int K) {
   return b;
 }
 
+size_t carved_bytes(const dyson_plan* p, int K) {
+  Work tmp;
+  return table_bytes(work_table(p, &tmp, K, p->kcap, false));
+}
+
+dyson_status carve_work(const dyson_plan* p, Work* w, int K, char* base, size_t cap) {
+  const size_t need = carved_bytes(p, K);
+  if (need > cap)
+    return fail(DYSON_EINVAL, "the allocation-free solve of " + std::to_string(K) +
+                                  " frequencies on this plan needs " + std::to_string(need) +
+                                  " bytes of scratch; the maximum is " + std::to_string(cap));
+  w->plan = p;
+  w->carved = true;
+  size_t off = 0;
+  for (auto& e : work_table(p, w, K, p->kcap, false)) {
+    *e.first = base + off;
+    off += (e.second + 255) / 256 * 256;
+  }
+  if (p->hp.opts.precision == DYSON_PREC_FP64) w->fac64 = (double*)w->fac[0];
+  w->h_count = w->h_static;
+  w->Kcap = K;
+  w->kq = p->kcap;
+  w->bytes = off;
+  w->fac_g[0] = w->fac_g[1] = -1000;
+  return DYSON_OK;
+}
+
 void free_work(Work* w, hipStream_t s) {
+  if (w->carved) {  // slices of a region the Work does not own
+    *w = Work{};
+    return;
+  }
   const dyson_ctx* c = w->plan ? w->plan->ctx : nullptr;
   if (c) (void)hipSetDevice(c->device);
   for (size_t i = 0; i < w->sub.size(); ++i) {
@@ -269,7 +300,7 @@ dyson_status alloc_table(const dyson_plan* p, Work* w, int K, int kq, bool sub, 
     w->bytes += (e.second + 255) / 256 * 256;
   }
   if (p->hp.opts.precision == DYSON_PREC_FP64 && !sub) w->fac64 = (double*)w->fac[0];
-  HIPC(hipMemsetAsync(w->d_wprof, 0, 4 * (size_t)K * p->nmax * sizeof(unsigned long long), s));
+  launch_zero(w->d_wprof, 4 * (size_t)K * p->nmax * sizeof(unsigned long long), s);
   if (hipHostMalloc((void**)&w->h_count, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     w->h_count = nullptr;
@@ -284,6 +315,7 @@ dyson_status alloc_table(const dyson_plan* p, Work* w, int K, int kq, bool sub, 
 
 dyson_status ensure_work(const dyson_plan* p, Work* w, int K, hipStream_t s) {
   if (w->plan == p && K <= w->Kcap) return DYSON_OK;
+  if (w->carved) return fail(DYSON_EINVAL, "scratch workspace is smaller than the call");
   HIPC(hipSetDevice(p->ctx->device));
   free_work(w, s);
   dyson_status st = alloc_table(p, w, K, p->kcap, false, s);
@@ -485,9 +517,9 @@ struct Run {
 
   dyson_status reset_items(int level) {
     const size_t ni = (size_t)K * p->lv[level].n;
-    HIPC(hipMemsetAsync(w->lz_stopped, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(w->lz_steps, 0, ni * sizeof(int), s));
-    HIPC(hipMemsetAsync(w->lz_beta, 0, ni * 2 * sizeof(double), s));
+    launch_zero(w->lz_stopped, ni * sizeof(int), s);
+    launch_zero(w->lz_steps, ni * sizeof(int), s);
+    launch_zero(w->lz_beta, ni * 2 * sizeof(double), s);
     return DYSON_OK;
   }
 
@@ -526,7 +558,7 @@ struct Run {
     const size_t V = (size_t)K * HP.T * HP.S * 2;
     auto Qj = [&](int j) { return w->Q + (size_t)j * V; };
     CHECKED(reset_items(level));
-    HIPC(hipMemsetAsync(w->Dl, 0, V * sizeof(double), s));
+    launch_zero(w->Dl, V * sizeof(double), s);
     LzArgs a = lz_args(level);
     const int n_items = K * L.n;
     // |r^T r| <= brk |r|^2: redo the item; each further attempt accepts a
@@ -621,7 +653,7 @@ namespace dyson {
 
 dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int n, hipStream_t s) {
   const int N = p->hp.N;
-  HIPC(hipMemsetAsync(w->d_flag, 0, sizeof(int), s));
+  launch_zero(w->d_flag, sizeof(int), s);
   for (int j = 0; j < n; ++j) {
     if (sl[j].K < 1) return fail(DYSON_EINVAL, "K must be >= 1");
     if (!sl[j].V || !sl[j].omega || !sl[j].sigma || !sl[j].G)
@@ -652,8 +684,8 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   CHECKED(begin_call(p, w, K, s));
   const HostPlan& P = p->hp;
   w->prof.reset();
-  w->prof.on = P.opts.profile != 0;
-  if (w->prof.on) HIPC(hipMemsetAsync(w->d_prof, 0, 8 * sizeof(unsigned long long), s));
+  w->prof.on = P.opts.profile != 0 && !w->carved;
+  if (w->prof.on) launch_zero(w->d_prof, 8 * sizeof(unsigned long long), s);
   Run run{p, w, K, s};
   const size_t NP = (size_t)P.T * P.S;
   // a1: diagonal of H, each slice into its rows of the batch
@@ -664,7 +696,7 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   }
   // a3/a4: leaf factorization and diag(B^{-1})
   const size_t V = (size_t)K * NP * 2;
-  HIPC(hipMemsetAsync(w->gacc, 0, V * sizeof(double), s));
+  launch_zero(w->gacc, V * sizeof(double), s);
   // FP64 plans keep the leaf factors (FP64 buffers); mixed plans only take the
   // diagonal here and factor the preconditioner again in complex64
   const bool keep = P.opts.precision == DYSON_PREC_FP64;
@@ -676,7 +708,11 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   }
   // a5-a9: the corrections.  Each level adds its own diag(X_l); the levels
   // of a group run bottom-up, the groups concurrently on their own streams.
-  const auto groups = level_groups(p);
+  std::vector<std::vector<int>> groups = level_groups(p);
+  if (w->carved) {  // one group, bottom-up, on the call's stream
+    groups.assign(1, {});
+    for (int l = (int)P.levels.size() - 1; l >= 0; --l) groups[0].push_back(l);
+  }
   const int G = (int)groups.size();
   std::vector<dyson_status> gst(G, DYSON_OK);
   std::vector<std::string> gerr(G);
@@ -699,11 +735,10 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
       gw->fac_g[0] = gw->fac_g[1] = -1000;
       gw->prof.reset();
       gw->prof.on = w->prof.on;
-      if (hipStreamWaitEvent(gs, w->ev, 0) != hipSuccess ||
-          hipMemsetAsync(gw->gacc, 0, V * sizeof(double), gs) != hipSuccess ||
-          (gw->prof.on &&
-           hipMemsetAsync(gw->d_prof, 0, 8 * sizeof(unsigned long long), gs) != hipSuccess))
+      if (hipStreamWaitEvent(gs, w->ev, 0) != hipSuccess)
         st = fail(DYSON_EDEVICE, "level group set-up failed");
+      launch_zero(gw->gacc, V * sizeof(double), gs);
+      if (gw->prof.on) launch_zero(gw->d_prof, 8 * sizeof(unsigned long long), gs);
     }
     Run gr{p, gw, K, gs};
     for (int l : groups[g]) {
@@ -754,7 +789,7 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   if (nchk > 0) {
     const dyson_status saved = w->pending;
     w->pending = DYSON_OK;
-    HIPC(hipMemsetAsync(w->d_err, 0, sizeof(double), s));
+    launch_zero(w->d_err, sizeof(double), s);
     void* fac0 = nullptr;
     CHECKED(run.factors_for(0, 0, &fac0));
     for (int c = 0; c < nchk; ++c) {
@@ -852,6 +887,7 @@ dyson_status dyson_create(dyson_ctx** ctx, int device, size_t hbm_budget,
     hbm_budget = fr / 10 * 9;
   }
   c->budget = hbm_budget;
+  CHECKED(noalloc_init(device));
   *ctx = c.release();
   return DYSON_OK;
 }
@@ -1025,7 +1061,7 @@ dyson_status dyson_leaf_diag(dyson_plan* p, int K, const double* d_d, double* d_
   CHECKED(begin_call(p, w, K, s));
   launch_to_tile(p->geom, K, d_d, w->d, 1.0, s);
   const size_t V = (size_t)K * p->hp.T * p->hp.S * 2;
-  HIPC(hipMemsetAsync(w->gacc, 0, V * sizeof(double), s));
+  launch_zero(w->gacc, V * sizeof(double), s);
   launch_factor_diag(p->geom, K, w->d, w->fac64, w->gacc, s);
   launch_from_tile(p->geom, K, w->gacc, d_Gleaf, s);
   HIPC(hipGetLastError());
@@ -1042,7 +1078,7 @@ dyson_status dyson_xmatvec(dyson_plan* p, int level, int K, const double* d_d, c
   launch_to_tile(p->geom, K, d_d, w->d, 1.0, s);
   const size_t V = (size_t)K * p->hp.T * p->hp.S * 2;
   launch_to_tile(p->geom, K, d_q, w->R, 0.0, s);
-  HIPC(hipMemsetAsync(w->xH, 0, V * sizeof(double), s));
+  launch_zero(w->xH, V * sizeof(double), s);
   Run run{p, w, K, s};
   CHECKED(run.reset_items(level));
   CHECKED(run.xmatvec(level, w->R, w->xH));
