@@ -70,36 +70,64 @@ def traffic_for(kernel, workload, precision):
         return None
 
 
+def _oracle_one(args):
+    """One frequency of the oracle in a worker process (one BLAS thread)."""
+    dims, d_row, t = args
+    import oracle
+    return oracle.diag_inv_rgf(dims, d_row, t)
+
+
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
 def cpu_baseline(w, n_freq_sample, max_seconds=30.0):
     """The oracle (block-tridiagonal recursive Green's function, FP64) timed on
-    the host on a bounded sample of the same workload's frequencies."""
+    the host on a bounded sample of the same workload's frequencies: a process
+    pool over frequencies, one BLAS thread per worker, as many workers as this
+    process may run on (at most 16, the host share of one GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
     import numpy as np
 
     import oracle
     import synth
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
     V, om, sig = synth.make_inputs(w)
     d = oracle.assemble_diag(V, om, sig, w.mu)
-    done = 0
-    t0 = time.perf_counter()
-    results = {}
     # frequencies spread over the whole range, the lowest (slowest to
     # converge) and the highest included
     ks = sorted({int(round(x)) for x in np.linspace(0, w.n_freq - 1, min(n_freq_sample, w.n_freq))})
-    for k in ks:
-        results[k] = oracle.diag_inv_rgf(w.dims, d[k], w.t)
-        done += 1
-        if time.perf_counter() - t0 > max_seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=w.n_sites * done / dt, unit="site*freq/s", cores=threads, kind="oracle",
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16, len(ks)))
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"   # inherited by the spawned workers before numpy loads
+    results = {}
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                initializer=_one_blas_thread) as ex:
+        ex.submit(_one_blas_thread).result()          # workers started before the clock
+        t0 = time.perf_counter()
+        futs = {}
+        for k in ks:
+            futs[k] = ex.submit(_oracle_one, (tuple(w.dims), d[k], w.t))
+        for k in ks:
+            remaining = max_seconds * 4 - (time.perf_counter() - t0)
+            try:
+                results[k] = futs[k].result(timeout=max(remaining, 1.0))
+            except cf.TimeoutError:
+                break
+        dt = time.perf_counter() - t0
+        for f in futs.values():
+            f.cancel()
+    done = len(results)
+    return dict(value=w.n_sites * done / dt, unit="site*freq/s", cores=workers, kind="oracle",
                 sample=f"{done} of {w.n_freq} frequencies (k = {sorted(results)}) of the same "
-                       f"{w.dims[0]}x{w.dims[1]} "
-                       f"lattice, O2 recursive Green's function, FP64, {dt:.1f} s"), results
+                       f"{'x'.join(str(x) for x in w.dims)} lattice, O2 recursive Green's function, "
+                       f"FP64, process pool of {workers} workers with one BLAS thread each, "
+                       f"{dt:.1f} s"), results
 
 
 def serve_bench(args):
@@ -251,8 +279,11 @@ def main():
                          "levels in sequence")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=16)
-    ap.add_argument("--plain-baseline", action="store_true",
-                    help="also time the plain per-frequency FP64 solve on 4 sampled frequencies")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-frequency FP64 solve on 4 sampled frequencies")
+    ap.add_argument("--no-c64", action="store_true",
+                    help="skip the untimed complex64-preconditioner solve reported beside the "
+                         "complex32 one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -342,27 +373,27 @@ def main():
     # over the timed steps / its event-timed duration on its stream
     roof = None
     if not args.no_profile:
+        # roofline of the dominant kernel (the inner-solve update, k_cocg_update):
+        # algorithmic bytes it moved / its event-timed duration on its stream
         c = 0
+        tr = traffic_for(KERNEL_NAMES[c], args.workload, args.precision)
         ms = sum(r["kern_ms"][c] for r in reports)
         nb = sum(r["kern_bytes"][c] for r in reports)
         nl = sum(r["kern_launches"][c] for r in reports)
-        achieved = nb / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        tr = traffic_for(KERNEL_NAMES[c], args.workload, args.precision)
-        # the correction levels run in concurrent stream groups, so a launch's
-        # duration includes sharing the GPU; the algorithmic bytes of all hot
-        # kernel classes over the step's wall time give the path's own rate
+        a_sh = nb / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        # over the whole step: algorithmic bytes of all hot kernel classes / wall time
         all_b = sum(sum(r["kern_bytes"]) for r in reports) / args.steps
         path_gbs = all_b / (ms_per_step * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": KERNEL_NAMES[c], "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": tr, "algorithmic_bytes_per_launch": round(nb / max(nl, 1)),
-                "avg_launch_us": round(1000.0 * ms / max(nl, 1), 2), "launches": nl,
-                "hot_path_algorithmic_bytes_per_step": round(all_b),
-                "hot_path_GBps_over_step": round(path_gbs, 1),
-                "hot_path_frac": round(path_gbs / PEAK_HBM_GBS, 4)}
+        timed = {"level_streams": args.level_streams, "achieved": round(a_sh, 1),
+                 "frac": round(a_sh / PEAK_HBM_GBS, 4),
+                 "algorithmic_bytes_per_launch": round(nb / max(nl, 1)),
+                 "avg_launch_us": round(1000.0 * ms / max(nl, 1), 2), "launches": nl}
+        r1, t1 = None, None
         if args.level_streams > 1 and not args.no_standalone:
-            # the same kernel with nothing beside it: one untimed solve with the
-            # levels run one after another, so each launch has the GPU alone
+            # with concurrent level groups a launch shares the GPU with the
+            # other groups' kernels, so its duration is not its own: the kernel's
+            # rate comes from one untimed solve with the levels one after another
+            # (each launch alone on the GPU), every class timed
             ps = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                       inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=2,
                       level_streams=1)
@@ -371,21 +402,37 @@ def main():
             torch.cuda.synchronize()
             t1 = time.perf_counter() - t0
             ps.close()
+        if r1 is not None:
             ms1, nb1, nl1 = r1["kern_ms"][c], r1["kern_bytes"][c], r1["kern_launches"][c]
-            a1 = nb1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
-            per_class = {}
-            for ci, name in enumerate(KERNEL_NAMES):
-                m_, b_ = r1["kern_ms"][ci], r1["kern_bytes"][ci]
-                g_ = b_ / (m_ * 1e-3) / 1e9 if m_ > 0 else 0.0
-                per_class[name] = {"GBps": round(g_, 1), "frac": round(g_ / PEAK_HBM_GBS, 4),
-                                   "launches": r1["kern_launches"][ci]}
-            roof["standalone"] = {"level_streams": 1, "achieved": round(a1, 1),
-                                  "frac": round(a1 / PEAK_HBM_GBS, 4),
-                                  "avg_launch_us": round(1000.0 * ms1 / max(nl1, 1), 2),
-                                  "launches": nl1, "solve_s": round(t1, 3),
-                                  "kernels": per_class}
-            log(f"standalone {KERNEL_NAMES[c]}: {a1:.1f} GB/s over {nl1} launches "
-                f"(levels in sequence, {t1:.2f} s)")
+            where = ("one untimed solve with the correction levels in sequence (each launch "
+                     "alone on the GPU), HIP events on the launch stream")
+        else:
+            ms1, nb1, nl1 = ms, nb, nl
+            where = "the timed steps, HIP events on the launch stream"
+        a1 = nb1 / (ms1 * 1e-3) / 1e9 if ms1 > 0 else 0.0
+        per_class = {}
+        src = r1 if r1 is not None else {k: [sum(r[k][i] for r in reports) for i in range(4)]
+                                         for k in ("kern_ms", "kern_bytes", "kern_launches")}
+        for ci, name in enumerate(KERNEL_NAMES):
+            m_, b_ = src["kern_ms"][ci], src["kern_bytes"][ci]
+            if m_ <= 0:
+                continue
+            g_ = b_ / (m_ * 1e-3) / 1e9
+            per_class[name] = {"GBps": round(g_, 1), "frac": round(g_ / PEAK_HBM_GBS, 4),
+                               "launches": src["kern_launches"][ci],
+                               "avg_launch_us": round(1000.0 * m_ / max(src["kern_launches"][ci], 1), 2)}
+        roof = {"bound": "hbm", "kernel": KERNEL_NAMES[c], "achieved": round(a1, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(a1 / PEAK_HBM_GBS, 4),
+                "traffic": tr, "algorithmic_bytes_per_launch": round(nb1 / max(nl1, 1)),
+                "avg_launch_us": round(1000.0 * ms1 / max(nl1, 1), 2), "launches": nl1,
+                "measured_in": where, "kernels": per_class,
+                "standalone_solve_s": round(t1, 3) if t1 is not None else None,
+                "shared_gpu_timed_steps": timed,
+                "hot_path_algorithmic_bytes_per_step": round(all_b),
+                "hot_path_GBps_over_step": round(path_gbs, 1),
+                "hot_path_frac": round(path_gbs / PEAK_HBM_GBS, 4)}
+        log(f"{KERNEL_NAMES[c]}: {a1:.1f} GB/s over {nl1} launches ({where}); "
+            f"in the timed steps {a_sh:.1f} GB/s")
 
     # accuracy against the oracle on a sample of frequencies (outside the timed region)
     cpu, err, value = None, None, work / (ms_per_step / 1000.0)
@@ -429,7 +476,7 @@ def main():
 
     # the plain form: one frequency per call, FP64 factors (sampled, extrapolated)
     plain = None
-    if args.plain_baseline:
+    if not args.no_plain:
         pp = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=PREC_FP64,
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol)
         ks = sorted({0, w.n_freq // 3, (2 * w.n_freq) // 3, w.n_freq - 1})
@@ -444,9 +491,36 @@ def main():
             log(f"plain fp64 single frequency k={k}: {secs[-1]:.3f} s")
         est = sum(secs) / len(secs) * w.n_freq
         plain = {"value": work / est, "unit": "site*freq/s", "sampled_freqs": ks,
+                 "batched_over_plain": round(value / (work / est), 2),
                  "s_per_freq": [round(x, 3) for x in secs],
                  "note": "one frequency per call, FP64 factors; mean of the samples x K"}
         pp.close()
+
+    # the same workload with complex64 preconditioner factors (untimed by the
+    # step clock: one warm-up solve, then one measured)
+    c64 = None
+    if not args.no_c64 and prec == PREC_MIXED16:
+        pc = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=PREC_MIXED,
+                  inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
+                  level_streams=args.level_streams)
+        Gc = torch.empty_like(G)
+        pc.solve(tV, tom, tsig, Gc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc = pc.solve(tV, tom, tsig, Gc, report=True)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        ec = None
+        if err is not None and len(w.dims) == 2 and not args.no_cpu:
+            import oracle
+            Gch = Gc.cpu().numpy()
+            ec = max(oracle.rel_err(Gch[k], ref[k]) for k in ref)
+        c64 = {"value": work / tc if rc["capped_items"] == 0 and rc["est_rel_err"] <= 1e-6
+               else 0.0, "unit": "site*freq/s", "s_per_solve": round(tc, 3),
+               "dtype": "c64 preconditioner + f64", "max_rel_err_sampled": ec,
+               "est_rel_err_device": rc["est_rel_err"]}
+        log(f"complex64 preconditioner: {tc:.3f} s per solve")
+        pc.close()
 
     lat_sorted = sorted(lat)
     out = {
@@ -469,6 +543,7 @@ def main():
         "est_rel_err_device": max(r["est_rel_err"] for r in reports),
         "capped_items": capped,
         "plain_fp64_per_frequency": plain,
+        "c64_preconditioner": c64,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
