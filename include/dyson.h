@@ -290,6 +290,24 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
 #define DYSON_AUTOTUNE_EDGES_3D {4, 5, 6}
 #define DYSON_AUTOTUNE_LEVEL_STREAMS {1, 3, 4}
 
+/* The standard domain-decomposition inverse the paper compares against
+ * (Sec. II.B, eqs. (4)-(6)): for a one-level decomposition (every separator in
+ * one interface; DYSON_PART_SINGLE, or any plan with at most one correction
+ * level) the Schur complement S = C - E^T B^{-1} E is formed explicitly (m x m
+ * complex, m = interface sites) and inverted, and
+ *   diag(H^{-1}) = diag(S^{-1}) on the interface,
+ *   diag(B^{-1}) + diag(B^{-1} E S^{-1} E^T B^{-1}) inside the subdomains.
+ * Arguments and layouts as dyson_solve (device pointers).  Every factor and
+ * product is FP64 whatever opts.precision says.  Device memory: about
+ * 16 K (m^2 + 64 m + T n_I S) bytes beyond the plan's workspace (T tiles of S
+ * sites, n_I interface sites around one leaf), allocated and freed within the
+ * call; DYSON_ENOMEM if that fails, DYSON_EUNSUPPORTED for a plan with more than
+ * one correction level.  The report gives t_total_ms, hbm_bytes and
+ * max_rank_used = m. */
+dyson_status dyson_solve_schur(dyson_plan* plan, int K, const double* d_V, const double* d_omega,
+                               const double* d_sigma, double* d_G, void* stream,
+                               dyson_report* report);
+
 /* Measured choice of the tile shape: for each candidate leaf edge
  * (DYSON_AUTOTUNE_EDGES_2D on chains and squares, DYSON_AUTOTUNE_EDGES_3D on
  * cubes; periodic axes keep only edges that divide them) and level-stream

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("dyson_solve", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_z", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_host", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
+    ("dyson_solve_schur", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_solve_noalloc", C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, C.POINTER(Report)]),
     ("dyson_noalloc_bytes", C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     ("dyson_noalloc_max_bytes", C.c_size_t, []),
@@ -210,6 +211,12 @@ def dyson_solve_noalloc(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
                         report: Report | None = None):
     _check(load_library().dyson_solve_noalloc(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
                                               C.byref(report) if report is not None else None))
+
+
+def dyson_solve_schur(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                      report: Report | None = None):
+    _check(load_library().dyson_solve_schur(plan, K, V_ptr, omega_ptr, sigma_ptr, G_ptr, stream,
+                                            C.byref(report) if report is not None else None))
 
 
 def dyson_noalloc_bytes(plan, K: int) -> int:
@@ -394,6 +401,18 @@ class Plan:
         rep = Report()
         dyson_solve_noalloc(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)),
                             _ptr(self._c(sigma)), _ptr(self._c(G)), _stream(), rep)
+        return (G, rep.as_dict()) if report else G
+
+    def solve_schur(self, V, omega, sigma, G=None, report=False):
+        """dyson_solve_schur: diag(H^{-1}) by the explicit Schur complement of a
+        one-level decomposition (eq. (6))."""
+        import torch
+        K = int(omega.shape[0])
+        if G is None:
+            G = torch.empty((K, self.n_sites), dtype=torch.complex128, device=V.device)
+        rep = Report()
+        dyson_solve_schur(self.plan, K, _ptr(self._c(V)), _ptr(self._c(omega)),
+                          _ptr(self._c(sigma)), _ptr(self._c(G)), _stream(), rep)
         return (G, rep.as_dict()) if report else G
 
     def noalloc_bytes(self, K):

@@ -47,6 +47,7 @@ struct Prof {
 };
 
 struct Server;
+struct SchurData;  // explicit-Schur path (schur.hip): interface lists of a plan
 
 // Workspace for up to Kcap frequencies of one plan.
 struct Work {
@@ -130,6 +131,7 @@ struct dyson_plan {
   std::vector<int> check_pos;  // tile positions of the sampled error check
   dyson::Work main;  // workspace of the blocking entry points
   dyson::Work carved;  // slices of the device's scratch array (dyson_solve_noalloc)
+  std::shared_ptr<dyson::SchurData> schur;  // built by the first dyson_solve_schur
   std::atomic<int> live_requests{0};
 };
 
@@ -173,6 +175,10 @@ dyson_status validate_slices(const dyson_plan* p, Work* w, const Slice* sl, int 
 // solve stops and returns DYSON_ECANCELLED.
 dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream_t s,
                        dyson_report* rep, const std::function<bool()>& abort);
+
+// Device memory through the context's allocator (hipMalloc without one).
+void* ctx_alloc(const dyson_ctx* c, size_t bytes, hipStream_t s);
+void ctx_free(const dyson_ctx* c, void* ptr, hipStream_t s);
 
 // Frees the idle serving workspaces sized for plan p (before p is destroyed).
 void serve_forget_plan(dyson_ctx* c, const dyson_plan* p);

@@ -182,6 +182,9 @@ void dev_free(const dyson_ctx* c, void* ptr, hipStream_t s) {
 
 namespace dyson {
 
+void* ctx_alloc(const dyson_ctx* c, size_t bytes, hipStream_t s) { return dev_alloc(c, bytes, s); }
+void ctx_free(const dyson_ctx* c, void* ptr, hipStream_t s) { dev_free(c, ptr, s); }
+
 std::vector<std::vector<int>> level_groups(const dyson_plan* p) {
   const HostPlan& P = p->hp;
   const int L = (int)P.levels.size();

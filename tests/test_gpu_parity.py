@@ -486,3 +486,42 @@ def test_sampled_error_estimate_tracks_accuracy():
     assert rep_t["truncated"] == 1 and rep_t["est_rel_err"] > 1e-4
     _, rep_n = _plan(w, 8, 0, 2, check_sites=0).solve(tV, tom, tsig, report=True)
     assert rep_n["est_rel_err"] == 0.0
+
+
+SCHUR_CASES = [((32, 32), 16), ((5, 5), 3), ((37, 29), 8), ((48, 33), 16), ((40,), 8),
+               ((16, 16), 16), ((9, 8, 7), 4), ((12, 12, 12), 6), ((11, 10, 9), 5)]
+
+
+@pytest.mark.parametrize("dims,s", SCHUR_CASES, ids=[f"{c[0]}-s{c[1]}" for c in SCHUR_CASES])
+def test_explicit_schur_vs_oracle(dims, s):
+    """The standard domain-decomposition inverse of Sec. II.B (eq. (6)): S
+    formed and inverted explicitly on a one-level decomposition; its diagonal
+    equals the oracle's and the low-rank method's."""
+    w = _case(dims, K=3, mu=1.0 if len(dims) == 3 else 0.5)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    p = _plan(w, s, PART_SINGLE, 0)
+    G, rep = p.solve_schur(tV, tom, tsig, report=True)
+    ref = oracle_G(w, V, om, sig)
+    err = oracle.rel_err(G.cpu().numpy(), ref)
+    m = p.info.max_m[0] if p.info.levels else 0
+    print(f"schur {dims} s={s} m={m} err={err:.2e} rep={rep}")
+    assert err < 1e-10
+    assert rep["max_rank_used"] == m
+    Glr = p.solve(tV, tom, tsig).cpu().numpy()
+    assert oracle.rel_err(Glr, ref) < 1e-10
+
+
+def test_explicit_schur_periodic_and_refusals():
+    w = _case((24, 32), K=2)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    per = (1, 1)
+    p = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=8, partition=PART_SINGLE, precision=0,
+             periodic=per)
+    G = p.solve_schur(tV, tom, tsig).cpu().numpy()
+    assert oracle.rel_err(G, _dense_periodic(w, V, om, sig, per)) < 1e-10
+    nested = _plan(_case((48, 48), K=1), 8, PART_NESTED, 0)
+    assert nested.info.levels > 1
+    V1, om1, sig1, tV1, tom1, tsig1 = device_inputs(_case((48, 48), K=1))
+    with pytest.raises(DysonError) as e:
+        nested.solve_schur(tV1, tom1, tsig1)
+    assert e.value.status == 6      # DYSON_EUNSUPPORTED: more than one correction level
