@@ -255,6 +255,70 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def schur_compare(args):
+    """Sec. III compares the low-rank correction with the explicit Schur-complement
+    decomposition (eq. (6)) in how they scale with N.  Same synthetic square
+    lattices (t = -1, mu = 0.5, trap 2e-4 (256/L)^2, beta = 20), four frequencies
+    spread over the 64-point grid, 16x16 subdomains, FP64 everywhere, library
+    default tolerances: the explicit path on the one-level decomposition, the
+    low-rank path on the same one-level decomposition (where it is affordable)
+    and on the recursive one.  Every result is checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1102_3137_amd import Plan, PART_NESTED, PART_SINGLE, PREC_FP64
+    dev = torch.device("cuda:0")
+    rows = []
+    for L in args.schur_sizes:
+        w = synth.Workload(dims=(L, L), t=-1.0, mu=0.5, vc=2e-4 * (256.0 / L) ** 2, beta=20.0,
+                           freq_index=(0, 21, 42, 63), seed=2, name=f"square {L}")
+        V, om, sig = synth.make_inputs(w)
+        tV, tom, tsig = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (V, om, sig))
+        _, ref = cpu_baseline(w, w.n_freq, max_seconds=120.0)
+        row = {"lattice": [L, L], "n_freq": w.n_freq}
+
+        def timed_run(fn):
+            fn()                                   # allocation and warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Gx, rep = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            import oracle
+            Gh = Gx.cpu().numpy()
+            return dt, max(oracle.rel_err(Gh[k], ref[k]) for k in ref), rep
+
+        ps = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=16, partition=PART_SINGLE, precision=PREC_FP64,
+                  profile=1)
+        m = ps.info.max_m[0]
+        dt, err, rep = timed_run(lambda: ps.solve_schur(tV, tom, tsig, report=True))
+        gj_tf = rep["kern_bytes"][0] / (rep["kern_ms"][0] * 1e-3) / 1e12 if rep["kern_ms"][0] else None
+        row["explicit_schur"] = {"interface_m": m, "s_per_solve": round(dt, 4), "max_rel_err": err,
+                                 "gauss_jordan_ms": round(rep["kern_ms"][0], 2),
+                                 "gauss_jordan_TFLOPs": round(gj_tf, 2) if gj_tf else None,
+                                 "gauss_jordan_frac_of_fp64_peak":
+                                     round(gj_tf / 78.6, 3) if gj_tf else None}
+        log(f"{L}^2 explicit Schur (m = {m}): {dt:.3f} s, err {err:.2e}, Gauss-Jordan "
+            f"{rep['kern_ms'][0]:.1f} ms = {gj_tf or 0:.2f} TFLOP/s")
+        if m <= args.schur_single_max_m:
+            dt, err, rep = timed_run(lambda: ps.solve(tV, tom, tsig, report=True))
+            row["lowrank_one_level"] = {"s_per_solve": round(dt, 4), "max_rel_err": err,
+                                        "lanczos_steps": rep["lanczos_steps"]}
+            log(f"{L}^2 low-rank, one level: {dt:.3f} s, err {err:.2e}")
+        ps.close()
+        pn = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=16, partition=PART_NESTED, precision=PREC_FP64)
+        dt, err, rep = timed_run(lambda: pn.solve(tV, tom, tsig, report=True))
+        row["lowrank_recursive"] = {"s_per_solve": round(dt, 4), "max_rel_err": err,
+                                    "levels": pn.info.levels}
+        log(f"{L}^2 low-rank, recursive: {dt:.3f} s, err {err:.2e}")
+        pn.close()
+        rows.append(row)
+    print(json.dumps({"metric": "s per solve (4 frequencies), explicit Schur vs low-rank",
+                      "unit": "s", "higher_is_better": False, "data": "synthetic",
+                      "dtype": "f64", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +359,12 @@ def main():
                     help="reduced: squares 64/128/256, cubes 16/24, K in [4, 16]; "
                          "full: squares 128/256/512, cubes 32/64, K in [16, 256]")
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--schur-compare", action="store_true",
+                    help="time the explicit Schur-complement path against the low-rank one on "
+                         "square lattices (--schur-sizes) instead")
+    ap.add_argument("--schur-sizes", type=int, nargs="+", default=[64, 128, 256])
+    ap.add_argument("--schur-single-max-m", type=int, default=2000,
+                    help="largest interface size at which the one-level low-rank run is timed")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -311,6 +381,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.schur_compare:
+        schur_compare(args)
         return
 
     import numpy as np

@@ -303,7 +303,9 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
  * sites, n_I interface sites around one leaf), allocated and freed within the
  * call; DYSON_ENOMEM if that fails, DYSON_EUNSUPPORTED for a plan with more than
  * one correction level.  The report gives t_total_ms, hbm_bytes and
- * max_rank_used = m. */
+ * max_rank_used = m; with opts.profile set, kern_ms[0] is the event-timed
+ * Gauss-Jordan inversion of S, kern_launches[0] its launches and kern_bytes[0]
+ * its algorithmic flops (8 m^3 per frequency: m^3 complex multiply-adds). */
 dyson_status dyson_solve_schur(dyson_plan* plan, int K, const double* d_V, const double* d_omega,
                                const double* d_sigma, double* d_G, void* stream,
                                dyson_report* report);

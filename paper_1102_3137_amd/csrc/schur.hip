@@ -498,6 +498,8 @@ extern "C" dyson_status dyson_solve_schur(dyson_plan* p, int K, const double* d_
   const size_t m = (size_t)sd.m;
   char* buf = nullptr;
   const size_t need = schur_bytes(p, K, sd);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  long long gj_launches = 0;
   if (m > 0) {
     buf = (char*)ctx_alloc(p->ctx, need + 2048, s);
     if (!buf) {
@@ -516,12 +518,19 @@ extern "C" dyson_status dyson_solve_schur(dyson_plan* p, int K, const double* d_
     k_schur_w<<<dim3((unsigned)sd.nI, (unsigned)P.T, (unsigned)K), 64, 0, s>>>(a);
     k_schur_s<<<dim3((unsigned)((m * m + 255) / 256), (unsigned)K), 256, 0, s>>>(a);
     const unsigned nt = (unsigned)((m + 63) / 64);
+    if (P.opts.profile && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)) {
+      (void)hipGetLastError();
+      ev[0] = ev[1] = nullptr;
+    }
+    if (ev[0]) (void)hipEventRecord(ev[0], s);
     for (int p0 = 0; p0 < (int)m; p0 += NB) {
       const int nbp = std::min<int>(NB, (int)m - p0);
       k_gj_pivot<<<(unsigned)K, 256, 0, s>>>(Sm, (int)m, p0, nbp, Qb);
       k_gj_panels<<<dim3(nt, (unsigned)K), 256, 0, s>>>(Sm, (int)m, p0, nbp, Qb, Rx, Cb);
       k_gj_update<<<dim3(nt, nt, (unsigned)K), 256, 0, s>>>(Sm, (int)m, p0, nbp, Rx, Cb);
+      gj_launches += 3;
     }
+    if (ev[1]) (void)hipEventRecord(ev[1], s);
     k_schur_diag<<<dim3((unsigned)P.T, (unsigned)K), 256, 0, s>>>(a, w->gacc);
   }
   launch_from_tile(p->geom, K, w->gacc, d_G, s);
@@ -533,8 +542,17 @@ extern "C" dyson_status dyson_solve_schur(dyson_plan* p, int K, const double* d_
               hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     return DYSON_EDEVICE;
   }
+  float gj_ms = 0.f;
+  if (ev[0] && ev[1] && hipEventElapsedTime(&gj_ms, ev[0], ev[1]) != hipSuccess) gj_ms = 0.f;
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
+    // profile: class 0 is the Gauss-Jordan inversion of S (HIP events on the
+    // call's stream), its bytes field the algorithmic flops, 8 m^3 per frequency
+    rep->kern_ms[0] = gj_ms;
+    rep->kern_launches[0] = gj_launches;
+    rep->kern_bytes[0] = 8.0 * (double)m * (double)m * (double)m * K;
     rep->levels = (int)P.levels.size();
     rep->max_rank_used = (int)m;
     rep->batches = 1;
