@@ -247,6 +247,16 @@ def test_three_oracle_tiers_agree(dims):
     G3 = od.diag_inv_sampled(dims, d, -1.0, sites)
     assert oracle.rel_err(G2, G1) < 1e-12
     assert oracle.rel_err(G3, G1[sites]) < 1e-12
+    every = np.arange(n)
+    G3nd = od.diag_inv_sampled(dims, d, -1.0, every, order="nd")
+    assert oracle.rel_err(G3nd, G1) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(13, 11), (9, 8, 7), (20,), (5, 9, 6)])
+def test_nested_dissection_order_is_a_permutation(dims):
+    """The relabelling O3 may factor with visits every site exactly once."""
+    p = od.nested_dissection_order(dims)
+    assert np.array_equal(np.sort(p), np.arange(int(np.prod(dims))))
 
 
 # ---------------------------------------------------------------- P11 (Fig. 1)
