@@ -399,6 +399,22 @@ dyson_status dyson_req_report(dyson_req* req, dyson_report* report);
  * and free the handle. */
 dyson_status dyson_release(dyson_req* req);
 
+/* Several plans in one blocking call (e.g. lattices of different sizes and
+ * dimensions, each with its own frequencies): request i = plan i with Ks[i]
+ * frequencies and DEVICE arrays d_V[i] [N_i], d_omega[i] [K_i], d_sigma[i]
+ * [K_i][N_i] and d_G[i] [K_i][N_i] (layouts as dyson_solve).  The inputs may
+ * be written on `stream`: it is synchronized first.  The requests go through
+ * the context's server as one arrival, so they are split into frequency
+ * batches by the HBM budget and run concurrently in its slots (continuous
+ * batching); each G equals its own dyson_submit result bit for bit.  All plans
+ * belong to one context.  Returns when every request has finished: the first
+ * error of any of them, with every request released; reports[i] (may be NULL)
+ * as dyson_req_report. */
+dyson_status dyson_solve_batch(int n, dyson_plan* const* plans, const int* Ks,
+                               const double* const* d_V, const double* const* d_omega,
+                               const double* const* d_sigma, double* const* d_G, void* stream,
+                               dyson_report* reports);
+
 const char* dyson_last_error(void);
 const char* dyson_version(void);
 

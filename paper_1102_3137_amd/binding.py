@@ -112,6 +112,8 @@ SIGNATURES = [
     ("dyson_cancel", C.c_int, [_P]),
     ("dyson_req_report", C.c_int, [_P, C.POINTER(Report)]),
     ("dyson_release", C.c_int, [_P]),
+    ("dyson_solve_batch", C.c_int, [C.c_int, C.POINTER(_P), _I, C.POINTER(_P), C.POINTER(_P),
+                                    C.POINTER(_P), C.POINTER(_P), _P, C.POINTER(Report)]),
     ("dyson_last_error", C.c_char_p, []),
     ("dyson_version", C.c_char_p, []),
 ]
@@ -526,6 +528,27 @@ class Context:
                                              C.byref(best), C.byref(rate)))
         return {"leaf_edge": best.leaf_edge, "level_streams": best.level_streams,
                 "rate": rate.value}
+
+    def solve_batch(self, items, report=False):
+        """dyson_solve_batch: items = [(plan, V, omega, sigma), ...] with torch
+        tensors on the GPU (plans of this context); returns the G tensors (and
+        the reports)."""
+        import torch
+        n = len(items)
+        outs = []
+        arr = lambda vals: (_P * n)(*vals)  # noqa: E731
+        for (p, V, om, sig) in items:
+            outs.append(torch.empty((int(om.shape[0]), p.n_sites), dtype=torch.complex128,
+                                    device=V.device))
+        reps = (Report * n)()
+        Ks = (C.c_int * n)(*[int(it[2].shape[0]) for it in items])
+        _check(load_library().dyson_solve_batch(
+            n, arr([it[0].plan for it in items]), Ks,
+            arr([Plan._c(it[1]).data_ptr() for it in items]),
+            arr([Plan._c(it[2]).data_ptr() for it in items]),
+            arr([Plan._c(it[3]).data_ptr() for it in items]),
+            arr([g.data_ptr() for g in outs]), _stream(), reps))
+        return (outs, [r.as_dict() for r in reps]) if report else outs
 
     def plan(self, dims, **kw) -> Plan:
         p = Plan(dims, ctx=self, **kw)

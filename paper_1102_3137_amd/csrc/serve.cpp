@@ -613,4 +613,44 @@ dyson_status dyson_release(dyson_req* req) {
   return DYSON_OK;
 }
 
+dyson_status dyson_solve_batch(int n, dyson_plan* const* plans, const int* Ks,
+                               const double* const* d_V, const double* const* d_omega,
+                               const double* const* d_sigma, double* const* d_G, void* stream,
+                               dyson_report* reports) {
+  if (n < 1 || !plans || !Ks || !d_V || !d_omega || !d_sigma || !d_G)
+    return fail(DYSON_EINVAL, "bad batch arguments");
+  dyson_ctx* ctx = plans[0] ? plans[0]->ctx : nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!plans[i] || plans[i]->ctx != ctx || !ctx)
+      return fail(DYSON_EINVAL, "every plan of a batch must belong to one context");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(DYSON_EDEVICE, "hipSetDevice failed");
+  // the inputs are read on the server's streams: complete them first
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(DYSON_EDEVICE, "caller stream failed");
+  std::vector<dyson_req*> reqs(n, nullptr);
+  dyson_status st = DYSON_OK;
+  std::string err;
+  for (int i = 0; i < n && st == DYSON_OK; ++i) {
+    st = submit(plans[i], Ks[i], d_V[i], d_omega[i], 0, d_sigma[i], d_G[i], DYSON_MEM_DEVICE,
+                &reqs[i]);
+    if (st != DYSON_OK) err = get_error();
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!reqs[i]) continue;
+    if (st != DYSON_OK) {
+      (void)dyson_release(reqs[i]);  // cancels what has not started
+      continue;
+    }
+    const dyson_status si = dyson_wait(reqs[i], -1.0);
+    if (si != DYSON_OK && st == DYSON_OK) {
+      st = si;
+      err = get_error();
+    }
+    if (reports) (void)dyson_req_report(reqs[i], &reports[i]);
+    (void)dyson_release(reqs[i]);
+  }
+  if (st != DYSON_OK) return fail(st, err);
+  return DYSON_OK;
+}
+
 }  // extern "C"

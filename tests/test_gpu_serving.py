@@ -313,3 +313,37 @@ def test_fp64_requests_match_solo():
     r.release()
     p.close()
     ctx.close()
+
+
+def test_solve_batch_mixed_lattices():
+    """dyson_solve_batch: square and cubic lattices of different sizes with
+    different frequency counts in one blocking call (an uneven batch); each
+    result equals its own blocking solve bit for bit and the oracle within
+    1e-10 (FP64)."""
+    ctx = Context(0, slots=3)
+    cases = [(_w((48, 33), 3, 31, beta=20.0), 16), (_w((9, 8, 7), 2, 32), 4),
+             (_w((37, 29), 4, 33), 8), (_w((12, 12, 12), 2, 34), 6), (_w((64, 64), 5, 35), 16)]
+    items, alone, data = [], [], []
+    for w, s in cases:
+        p = _plan(ctx, w, s, PART_NESTED, PREC_FP64)
+        V, om, sig, tV, tom, tsig = device_inputs(w)
+        alone.append(p.solve(tV, tom, tsig).cpu().numpy())
+        items.append((p, tV, tom, tsig))
+        data.append((w, V, om, sig))
+    Gs, reps = ctx.solve_batch(items, report=True)
+    for i, (G, rep) in enumerate(zip(Gs, reps)):
+        Gh = G.cpu().numpy()
+        assert np.array_equal(Gh, alone[i]), f"batch item {i} differs from its solo solve"
+        assert rep["batches"] >= 1 and rep["truncated"] == 0
+        w, V, om, sig = data[i]
+        assert oracle.rel_err(Gh, oracle_G(w, V, om, sig)) < 1e-10
+    # an invalid member fails the whole call, the others are released
+    w, V, om, sig = data[0]
+    bad = items[0][2].clone()
+    bad[0] = -1.0
+    with pytest.raises(DysonError) as e:
+        ctx.solve_batch([items[1], (items[0][0], items[0][1], bad, items[0][3])])
+    assert e.value.status == 1
+    for it in items:
+        it[0].close()
+    ctx.close()
