@@ -446,6 +446,112 @@ def batch_mix(args):
         "est_rel_err_device": est}), flush=True)
 
 
+def serve_sweep(args):
+    """The serving stream at several arrival rates: the same seeded requests
+    (lattices drawn from --sweep-squares / --sweep-cubes, K ~ U{--sweep-k},
+    beta ~ U[5, 40], fresh self-energy each) replayed at each rate in
+    --sweep-rates through a context whose HBM budget (--sweep-budget-gb) forces
+    the larger requests into several frequency batches.  Every served result
+    is compared bit for bit with the same request solved alone."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_1102_3137_amd import Context, PART_NESTED, PREC_MIXED16
+    dev = torch.device("cuda:0")
+    trace = synth.serving_trace(args.serve_n, 1.0, squares=tuple(args.sweep_squares),
+                                cubes=tuple(args.sweep_cubes), k_range=tuple(args.sweep_k))
+    reqs = []
+    for t_unit, w in trace:
+        V, om, sig = synth.make_inputs(w)
+        reqs.append(dict(t1=t_unit, w=w, x=tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                                                  for a in (V, om, sig))))
+    work = sum(r["w"].n_sites * r["w"].n_freq for r in reqs)
+
+    def plan_kw(w):
+        return dict(t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
+                    partition=PART_NESTED, precision=PREC_MIXED16, inner_tol=args.inner_tol,
+                    lanczos_tol=args.lanczos_tol)
+
+    ctx = Context(0)
+    plans = {}
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        w = r["w"]
+        if w.dims not in plans:
+            plans[w.dims] = ctx.plan(w.dims, **plan_kw(w))
+        r["alone"] = plans[w.dims].solve(*r["x"])
+        torch.cuda.synchronize()
+        log(f"alone {i + 1}/{len(reqs)}: {w.name} x {w.n_freq}")
+    t_alone = time.perf_counter() - t0
+    ctx.close()
+    small = min(range(len(reqs)), key=lambda i: reqs[i]["w"].n_sites)
+    w = reqs[small]["w"]
+    V, om, sig = synth.make_inputs(w)
+    ks = [0, w.n_freq - 1]
+    ref = oracle.oracle_diag(w.dims, oracle.assemble_diag(V, om, sig, w.mu)[ks], w.t)
+    err = oracle.rel_err(reqs[small]["alone"].cpu().numpy()[ks], ref)
+    rows = []
+    budget = int(args.sweep_budget_gb * (1 << 30))
+    for rate in args.sweep_rates:
+        ctx = Context(0, hbm_budget=budget, slots=args.serve_slots)
+        plans = {}
+        for r in reqs:
+            if r["w"].dims not in plans:
+                plans[r["w"].dims] = ctx.plan(r["w"].dims, **plan_kw(r["w"]))
+        handles = [None] * len(reqs)
+
+        def submitter(start):
+            for i, r in enumerate(reqs):
+                delay = start + r["t1"] / rate - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                handles[i] = plans[r["w"].dims].submit(*r["x"])
+
+        start = time.perf_counter()
+        th = threading.Thread(target=submitter, args=(start,))
+        th.start()
+        th.join()
+        lat, qw, nb, ests, bad = [], [], [], [], 0
+        for i, h in enumerate(handles):
+            G = h.wait()
+            rep = h.report()
+            lat.append(rep["t_total_ms"] / 1000.0)
+            qw.append(rep["t_queue_ms"] / 1000.0)
+            nb.append(rep["batches"])
+            ests.append(rep["est_rel_err"])
+            bad += int(not torch.equal(G, reqs[i]["alone"]))
+        t_served = time.perf_counter() - start
+        for h in handles:
+            h.release()
+        ctx.close()
+        q = lambda a, f: float(np.quantile(np.array(a), f))  # noqa: E731
+        ok = bad == 0 and err <= 1e-6 and max(ests) <= 1e-6
+        rows.append({"rate_per_s": rate, "value": work / t_served if ok else 0.0,
+                     "served_s": round(t_served, 3),
+                     "latency_s": {"p50": round(q(lat, 0.5), 3), "p99": round(q(lat, 0.99), 3)},
+                     "queue_wait_s": {"p50": round(q(qw, 0.5), 3), "p99": round(q(qw, 0.99), 3)},
+                     "batches_per_request": {"mean": float(np.mean(nb)), "max": int(max(nb))},
+                     "mismatches_vs_alone": bad, "est_rel_err_device": max(ests)})
+        log(f"rate {rate}/s: {t_served:.2f} s, p50 {q(lat, 0.5):.2f} s, p99 {q(lat, 0.99):.2f} s, "
+            f"batches/request max {max(nb)}, mismatches {bad}")
+    print(json.dumps({
+        "metric": "served G_ii sites*freqs/sec at rel err <= 1e-6 vs FP64 oracle; p50/p99 request "
+                  "latency, per arrival rate", "unit": "site*freq/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "c32 preconditioner + f64", "data": "synthetic",
+        "config": {"workload": f"seeded stream of {len(reqs)} requests, squares "
+                               f"{args.sweep_squares}, cubes {args.sweep_cubes}, K in "
+                               f"{args.sweep_k}, beta in [5, 40]",
+                   "hbm_budget_gb": args.sweep_budget_gb, "slots": args.serve_slots,
+                   "requests": [f"{r['w'].name} x {r['w'].n_freq}" for r in reqs]},
+        "alone_one_after_another_s": round(t_alone, 3), "oracle_check": {"request": small,
+                                                                           "max_rel_err": err},
+        "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -486,6 +592,13 @@ def main():
                     help="reduced: squares 64/128/256, cubes 16/24, K in [4, 16]; "
                          "full: squares 128/256/512, cubes 32/64, K in [16, 256]")
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="the serving stream at every rate of --sweep-rates instead")
+    ap.add_argument("--sweep-rates", type=float, nargs="+", default=[0.1, 1.0, 10.0, 200.0])
+    ap.add_argument("--sweep-squares", type=int, nargs="+", default=[128, 256, 512])
+    ap.add_argument("--sweep-cubes", type=int, nargs="+", default=[32])
+    ap.add_argument("--sweep-k", type=int, nargs=2, default=[8, 24])
+    ap.add_argument("--sweep-budget-gb", type=float, default=24.0)
     ap.add_argument("--batch-mix", action="store_true",
                     help="the uneven multi-lattice batch (64^2..512^2, 24^3..48^3) in one "
                          "dyson_solve_batch call instead")
@@ -524,6 +637,9 @@ def main():
         return
     if args.batch_mix:
         batch_mix(args)
+        return
+    if args.serve_sweep:
+        serve_sweep(args)
         return
 
     import numpy as np
