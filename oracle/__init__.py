@@ -13,7 +13,8 @@ dyson    -- the definition (eq. (1)) and three independent ways to take the
 lowrank  -- a plain mirror of the paper's Lanczos-based low-rank correction
             method (Sec. II.B-C, eqs. (4)-(13)) with exact sparse solves; it is
             used to pin the oracle's agreement with the method at full
-            interface rank, not as an oracle of G itself.
+            interface rank, not as an oracle of G itself; and the Lanczos run
+            on the Schur complement (interface space) as a studied variant.
 
 Every function cites the passage of the paper it follows.  "parity unpinned"
 marks a function with no independent pin (none at present).
@@ -21,10 +22,10 @@ marks a function with no independent pin (none at present).
 from .dyson import (assemble_diag, assemble_diag_z, hamiltonian, dense_hamiltonian, diag_inv_dense,
                     diag_inv_rgf, diag_inv_sampled, closed_form_periodic,
                     closed_form_open_uniform, closed_form_uniform, oracle_diag, rel_err)
-from .lowrank import lowrank_diag, separator_positions, plan_boxes
+from .lowrank import lowrank_diag, interface_lanczos_diag, separator_positions, plan_boxes
 
 __all__ = ["assemble_diag", "assemble_diag_z", "hamiltonian", "dense_hamiltonian", "diag_inv_dense",
            "diag_inv_rgf", "diag_inv_sampled", "closed_form_periodic",
            "closed_form_open_uniform", "closed_form_uniform", "oracle_diag", "rel_err",
-           "lowrank_diag",
+           "lowrank_diag", "interface_lanczos_diag",
            "separator_positions", "plan_boxes"]
