@@ -135,6 +135,13 @@ typedef struct {
                          1/breakdown_tol, amplifying rounding by as much) is
                          redone from a fresh start vector; each later attempt
                          uses a 100x smaller threshold [1e-4] */
+  int interface_lanczos; /* 0: bilinear Lanczos on X (eqs. (8)-(12): two inner solves
+                         per step, the diagonal streamed from the basis); 1: on the
+                         Schur complement S = C - E^T B^{-1} E of each domain (from
+                         eqs. (5)-(7)): one inner solve per step, exactly m steps, the
+                         projected Hessenberg matrix H inverted once per (domain,
+                         frequency) and diag(X) = diag(V H^{-1} V^T) with
+                         V = [B^{-1} E P; P] [0] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */

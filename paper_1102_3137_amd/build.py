@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdyson_mi355x.so")
-SOURCES = ["plan.cpp", "kernels.hip", "cocg.hip", "solver.cpp", "serve.cpp", "noalloc.hip", "schur.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "cocg.hip", "solver.cpp", "serve.cpp", "noalloc.hip", "schur.hip", "iface.hip"]
 ARCH = os.environ.get("DYSON_OFFLOAD_ARCH", "gfx950")
 
 

@@ -30,6 +30,7 @@ struct DevLevel {
   int* tlo = nullptr;
   int* thi = nullptr;
   int* mcap = nullptr;
+  int* m = nullptr;     // interface size of each domain
 };
 
 // Event-timed kernel classes (report.kern_*).
@@ -65,6 +66,10 @@ struct Work {
   CocgState cst{};
   int *lz_stopped = nullptr, *lz_steps = nullptr, *lz_reorth = nullptr, *lz_armed = nullptr;
   double* Dl = nullptr;  // diagonal correction of the level being run
+  // Lanczos on the Schur complement: step vectors v_j = p_j + B^{-1} E p_j, the
+  // projected Hessenberg matrices (one per item) and the inversion's scratch
+  double *Vb = nullptr, *Hm = nullptr, *gjC = nullptr, *gjR = nullptr, *gjQ = nullptr;
+  int* f1mask = nullptr;  // skip array of the fresh-direction continuation
   double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
          *lz_scal = nullptr;
   int* d_count = nullptr;

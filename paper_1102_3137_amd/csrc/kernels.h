@@ -80,6 +80,7 @@ struct LzArgs {
   int* reorth;      // [n_items] 1 if the second Gram-Schmidt pass runs for the item
   int* armed;       // [n_items] 1 after a step whose residual passed the L2 stop test:
                     // the next step confirms exhaustion (|X q| at the noise level)
+  int iface;        // 1: Lanczos on the Schur complement (exactly m steps per item)
 };
 
 // Zeroes `bytes` bytes (a multiple of 4) at device address p on stream s.
@@ -112,7 +113,8 @@ void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s);
 void launch_count_open(const int* done, int n, int* out, hipStream_t s);
 
 void launch_freq_keys(const double* omega, int zmode, int K, uint64_t* fkey, hipStream_t s);
-void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s);
+void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s,
+                      int real_only = 0);
 void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s);
 void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,
                       hipStream_t s);
@@ -135,6 +137,21 @@ void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStre
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
                        int op, int j, double tol, double brk, int force, hipStream_t s);
 void launch_lz_reopen(const LzArgs& a, int K, double* D, hipStream_t s);
+// Lanczos on the Schur complement (iface.hip)
+void launch_f1_rhs(const LzArgs& a, int K, const double* p, double* rhs, hipStream_t s);
+void launch_f1_smat(const LzArgs& a, int K, const double* d, const double* p, const double* u,
+                    double* sv, double* v, hipStream_t s);
+void launch_f1_hcol(const LzArgs& a, double* Hm, int mm, int j, int op, hipStream_t s);
+void launch_f1_mask(const LzArgs& a, int* mask, hipStream_t s);
+void launch_f1_settle(const LzArgs& a, hipStream_t s);
+void launch_f1_hzero(const LzArgs& a, double* Hm, int mm, hipStream_t s);
+void launch_f1_hpad(const LzArgs& a, double* Hm, int mm, hipStream_t s);
+void launch_f1_diag(const LzArgs& a, int K, const double* Vb, size_t qstride, const double* Minv,
+                    int mm, double* D, hipStream_t s);
+// In-place inverse of `batch` m x m complex matrices (schur.hip); scratch Cb
+// [batch][m][32], Rx [batch][32][m], Qb [batch][32][32] complex.
+void launch_gj_invert(double* A, int m, int batch, double* Cb, double* Rx, double* Qb,
+                      hipStream_t s);
 void launch_add_into(const LzArgs& a, int K, const double* D, double* G, hipStream_t s);
 // Sampled check: b = e_pos in every frequency row; err = max(err, max_k |x - g| / |x|) at pos.
 void launch_unit_vector(const TileGeom& G, int K, int pos, double* b, hipStream_t s);

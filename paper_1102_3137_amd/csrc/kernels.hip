@@ -271,10 +271,11 @@ __global__ void k_count_open(const int* __restrict__ done, int n, int* __restric
   const size_t NP = (size_t)a.G.T * a.G.S;          \
   const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
 
-// Start vector: seeded random complex entries on the level's separator
-// sites (the interface C of eq. (4)) of every correction domain, zero
-// elsewhere; partial q^T q.
-__global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict__ q, uint64_t salt) {
+// Start vector: seeded random complex entries (real ones if real_only) on
+// the level's separator sites (the interface C of eq. (4)) of every
+// correction domain, zero elsewhere; partial q^T q.
+__global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict__ q, uint64_t salt,
+                                                   int real_only) {
   LZ_ITEM();
   const TileGeom& G = a.G;
   const int tid = threadIdx.x;
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict_
       const uint64_t key = splitmix64(a.seed ^ (salt * 0xD1B54A32D192ED03ULL) ^ a.fkey[k]) ^
                            (((uint64_t)a.level << 40) + (uint64_t)G.site_of[p]);
       const uint64_t h1 = splitmix64(key), h2 = splitmix64(h1 ^ 0xA5A5A5A5A5A5A5A5ULL);
-      v = cmk(2.0 * u01(h1) - 1.0, 2.0 * u01(h2) - 1.0);
+      v = cmk(2.0 * u01(h1) - 1.0, real_only ? 0.0 : 2.0 * u01(h2) - 1.0);
     }
     st(q, base + tid, v);
     qq = cmul(v, v);
@@ -378,10 +379,12 @@ __global__ __launch_bounds__(256) void k_lz_recur(LzArgs a, const double* __rest
   const cd al = ld(a.alpha, item), be = ld(a.beta, item);
   const cd qv = ld(q, base + tid);
   const cd qp = qprev ? ld(qprev, base + tid) : cmk(0.0, 0.0);
-  cd gv = ld(D, base + tid);
-  gv = cadd(gv, cmul(al, cmul(qv, qv)));
-  gv = cadd(gv, cscale(cmul(be, cmul(qp, qv)), 2.0));
-  st(D, base + tid, gv);
+  if (D) {  // the X form's streamed diagonal (the interface form takes it at the end)
+    cd gv = ld(D, base + tid);
+    gv = cadd(gv, cmul(al, cmul(qv, qv)));
+    gv = cadd(gv, cscale(cmul(be, cmul(qp, qv)), 2.0));
+    st(D, base + tid, gv);
+  }
   cd rv = csub(ld(u, base + tid), cmul(al, qv));
   rv = csub(rv, cmul(be, qp));
   st(r, base + tid, rv);
@@ -491,8 +494,10 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
     const cd rn = csub(ld(r, base + tid), acc);
     st(r, base + tid, rn);
     rr = cabs2(rn);
-    const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
-    st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
+    if (D) {
+      const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
+      st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
+    }
   }
   if (pass == 0) {
     cd s0 = cmk(rr, 0.0), s1 = cmk(0.0, 0.0);
@@ -553,6 +558,8 @@ __global__ void k_lz_next(LzArgs a, const double* __restrict__ r, double* __rest
 //   op 1: alpha   alpha = q^T u, unorm2 = |u|^2; an armed item whose new
 //                 |u| = |X q_j| is at the noise level stops here (exhausted)
 //   op 2: norms   stop test, beta_{j+1} = principal sqrt(r^T r)
+//   op 3: (interface form) beta of a fresh direction after an invariant
+//         subspace
 //
 // Stopping (Sec. II.C: the coefficients vanish once the Krylov space of X is
 // exhausted).  A residual that passes the L2 test |r| <= tol |u| may also be
@@ -599,7 +606,7 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     return;
   }
   if (op == 1) {
-    if (a.armed[item]) {
+    if (!a.iface && a.armed[item]) {
       // the confirming step: |u|^2 <= tol |X|^2 (|u| <= sqrt(tol) max|u|)
       if (s1.x <= tol * a.umax2[item]) {
         a.stopped[item] = 1;  // exhausted; this step contributes nothing
@@ -612,10 +619,49 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     a.umax2[item] = fmax(a.umax2[item], s1.x);
     return;
   }
+  if (op == 3) {
+    // interface form, fresh direction after an invariant subspace (armed ==
+    // 2): its normalization, or armed = 3 when its bilinear norm vanishes
+    if (s0.x == 0.0 || sqrt(cabs2(s1)) <= brk * s0.x) {
+      a.armed[item] = 3;
+      return;
+    }
+    st(a.beta, item, csqrt_p(s1));
+    return;
+  }
   const int steps = j + 1;
   a.steps[item] = steps;
   if (force) {
     a.stopped[item] = 3;  // test hook: breakdown declared at this step
+    return;
+  }
+  if (a.iface) {
+    // Lanczos on the Schur complement S (m x m, non-singular): after m steps
+    // the basis spans the whole interface space and S^{-1} = P H^{-1} P^T
+    // exactly; a residual that vanishes earlier means the start vector lay
+    // in an invariant subspace, so the item is redone from a fresh vector
+    const double rn = sqrt(s0.x), un = sqrt(a.unorm2[item]);
+    if (steps >= mcap[node]) {
+      a.stopped[item] = 1;
+      return;
+    }
+    if (un == 0.0) {
+      a.stopped[item] = 3;
+      return;
+    }
+    if (rn <= tol * un) {
+      // the basis spans an invariant subspace of S (a repeated eigenvalue
+      // limits the Krylov space): the subdiagonal entry is zero and the
+      // basis continues from a fresh direction orthogonal to it
+      a.armed[item] = 2;
+      st(a.beta, item, cmk(1.0, 0.0));
+      return;
+    }
+    if (sqrt(cabs2(s1)) <= brk * s0.x) {
+      a.stopped[item] = 3;
+      return;
+    }
+    st(a.beta, item, csqrt_p(s1));
     return;
   }
   // the residual far below the largest |u| seen (an estimate of |X|), or a
@@ -759,8 +805,9 @@ void launch_count_open(const int* done, int n, int* out, hipStream_t s) {
 void launch_freq_keys(const double* omega, int zmode, int K, uint64_t* fkey, hipStream_t s) {
   k_freq_keys<<<(K + 63) / 64, 64, 0, s>>>(omega, zmode, K, fkey);
 }
-void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s) {
-  k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, salt);
+void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s,
+                      int real_only) {
+  k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, salt, real_only);
 }
 void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s) {
   k_lz_scale<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q);

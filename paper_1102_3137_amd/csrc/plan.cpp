@@ -47,6 +47,7 @@ dyson_opts merge_opts(const dyson_opts* u) {
   o.fault_step = u->fault_step;
   o.fault_attempts = u->fault_attempts;
   if (u->breakdown_tol > 0) o.breakdown_tol = u->breakdown_tol;
+  o.interface_lanczos = u->interface_lanczos;
   return o;
 }
 
@@ -85,6 +86,10 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
     return "fault_step must be >= 0 and fault_attempts in [0, 3]";
   if (!(opts.breakdown_tol > 0.0 && opts.breakdown_tol < 1.0))
     return "breakdown_tol must be in (0, 1)";
+  if (opts.interface_lanczos != 0 && opts.interface_lanczos != 1)
+    return "interface_lanczos must be 0 or 1";
+  if (opts.interface_lanczos && opts.max_rank > 0)
+    return "the interface form runs to full rank (max_rank must be 0)";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];
   if (n > (1LL << 28)) return "lattice too large";
 

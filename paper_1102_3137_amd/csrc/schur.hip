@@ -448,6 +448,20 @@ dyson_status build_schur(const dyson_plan* pl, std::shared_ptr<SchurData>* out) 
 
 }  // namespace
 
+// In-place inverse of `batch` m x m complex matrices (contiguous, row-major),
+// blocked Gauss-Jordan without pivoting; Cb [batch][m][32], Rx [batch][32][m]
+// and Qb [batch][32][32] complex are scratch.
+void launch_gj_invert(double* A, int m, int batch, double* Cb, double* Rx, double* Qb,
+                      hipStream_t s) {
+  const unsigned nt = (unsigned)((m + 63) / 64);
+  for (int p0 = 0; p0 < m; p0 += NB) {
+    const int nbp = std::min<int>(NB, m - p0);
+    k_gj_pivot<<<(unsigned)batch, 256, 0, s>>>(A, m, p0, nbp, Qb);
+    k_gj_panels<<<dim3(nt, (unsigned)batch), 256, 0, s>>>(A, m, p0, nbp, Qb, Rx, Cb);
+    k_gj_update<<<dim3(nt, nt, (unsigned)batch), 256, 0, s>>>(A, m, p0, nbp, Rx, Cb);
+  }
+}
+
 size_t schur_bytes(const dyson_plan* p, int K, const SchurData& sd) {
   const size_t m = (size_t)sd.m;
   return (size_t)K * (m * m + 2 * m * NB + NB * NB + (size_t)p->hp.T * sd.nI * p->hp.S) * 16;

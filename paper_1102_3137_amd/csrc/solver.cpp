@@ -141,6 +141,23 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->d_prof, 64},         {(void**)&w->d_wprof, 4 * ni * 8},
       {(void**)&w->d_fkey, (size_t)K * 8}, {(void**)&w->stage_om, (size_t)K * 16},
       {(void**)&w->d_flag, 16},        {(void**)&w->d_err, 16}};
+  if (P.opts.interface_lanczos) {
+    // per level: n_nodes items of an mm x mm Hessenberg matrix (mm = the
+    // level's largest interface) and the inversion's panels
+    size_t hm = 0, pan = 0;
+    for (const auto& L : P.levels) {
+      size_t mm = 0;
+      for (int m : L.m) mm = std::max<size_t>(mm, (size_t)m);
+      hm = std::max(hm, (size_t)L.n_nodes * mm * mm);
+      pan = std::max(pan, (size_t)L.n_nodes * mm * 32);
+    }
+    t.push_back({(void**)&w->Vb, V * nq});
+    t.push_back({(void**)&w->Hm, (size_t)K * hm * 16});
+    t.push_back({(void**)&w->gjC, (size_t)K * pan * 16});
+    t.push_back({(void**)&w->gjR, (size_t)K * pan * 16});
+    t.push_back({(void**)&w->gjQ, ni * 32 * 32 * 16});
+    t.push_back({(void**)&w->f1mask, ni * 4});
+  }
   if (sub) {
     std::vector<std::pair<void**, size_t>> keep;
     for (auto& e : t)
@@ -541,14 +558,121 @@ struct Run {
   // Full re-orthogonalization of r against the basis: classical Gram-Schmidt,
   // repeated for the items whose first pass removed most of r (|r'| <
   // |r| / sqrt 2), which keeps the basis orthogonal to working precision.
-  void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
+  // after_reduce(pass) runs once the pass's coefficients are in a.h; D (the
+  // streamed diagonal of the X form) may be null.
+  // eta2 > 1 makes the second pass unconditional.
+  template <typename Hook>
+  void cgs2(const LzArgs& a, const DevLevel& L, int nvec, double* D, Hook after_reduce,
+            double eta2 = 0.5) {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
       timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, pass, s); });
       launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, pass, s);
-      timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, w->Dl, pass, s); });
-      if (pass == 0) launch_cgs_decide(a, K, L.tlo, L.thi, nvec, 0.5, s);
+      after_reduce(pass);
+      timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, D, pass, s); });
+      if (pass == 0) launch_cgs_decide(a, K, L.tlo, L.thi, nvec, eta2, s);
     }
+  }
+  void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
+    cgs2(a, L, nvec, w->Dl, [](int) {});
+  }
+
+  // One correction level in the interface form: bilinear Lanczos on the
+  // Schur complement S of every (domain, frequency) for exactly m steps
+  // (S p = (H (p - B^{-1} E p))|_C: one inner solve per step), the projected
+  // Hessenberg matrix H accumulated per item, then H^{-1} for every item at
+  // once and diag(X) = diag(V H^{-1} V^T) added to the running diagonal.  An
+  // item whose bilinear form breaks down (or whose residual vanishes before
+  // m steps) is redone from a fresh start vector, at most twice.
+  dyson_status lanczos_level_iface(int level, std::vector<int>* steps_out) {
+    const DevLevel& L = p->lv[level];
+    const HostPlan& HP = P();
+    const size_t V = (size_t)K * HP.T * HP.S * 2;
+    auto Qj = [&](int j) { return w->Q + (size_t)j * V; };
+    auto Vj = [&](int j) { return w->Vb + (size_t)j * V; };
+    CHECKED(reset_items(level));
+    launch_zero(w->Dl, V * sizeof(double), s);
+    LzArgs a = lz_args(level);
+    a.iface = 1;
+    const int n_items = K * L.n;
+    int mm = 0;
+    for (int m : HP.levels[level].m) mm = std::max(mm, m);
+    launch_zero(w->Hm, (size_t)n_items * mm * mm * 16, s);
+    double brk = HP.opts.breakdown_tol;
+    std::vector<int> st(n_items), stop(n_items);
+    void* facB = nullptr;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      if (attempt > 0) launch_f1_hzero(a, w->Hm, mm, s);
+      launch_lz_random(a, K, Qj(0), (uint64_t)attempt, s);
+      launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 0, 0, HP.opts.lanczos_tol, brk, 0, s);
+      launch_lz_scale(a, K, Qj(0), s);
+      HIPC(hipGetLastError());
+      for (int j = 0; j < mm; ++j) {
+        int open = 0;
+        CHECKED(count_open(w->lz_stopped, n_items, &open));
+        if (open == 0) break;
+        const double* q = Qj(j);
+        launch_f1_rhs(a, K, q, w->rhs, s);                       // E p
+        CHECKED(factors_for(level + 1, level, &facB));
+        CHECKED(cocg(level, level + 1, facB, w->rhs, w->xB));    // u = B^{-1} E p
+        if (w->pending != DYSON_OK) break;
+        launch_f1_smat(a, K, w->d, q, w->xB, w->xH, Vj(j), s);   // S p, v = p + u
+        launch_lz_alpha(a, K, q, w->xH, s);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 1, j, HP.opts.lanczos_tol, brk, 0, s);
+        launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, w->xH, w->R, nullptr, s);
+        cgs2(a, L, j + 1, nullptr, [&](int pass) { launch_f1_hcol(a, w->Hm, mm, j, pass, s); });
+        launch_lz_norms(a, K, w->R, s);
+        const int force = (HP.opts.fault_step == j + 1 && attempt < HP.opts.fault_attempts);
+        launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 2, j, HP.opts.lanczos_tol, brk, force, s);
+        launch_f1_hcol(a, w->Hm, mm, j, 2, s);
+        if (j + 1 < w->kq) launch_lz_next(a, K, w->R, Qj(j + 1), s);
+        HIPC(hipGetLastError());
+        // items whose basis met an invariant subspace go on from a fresh
+        // real random direction, orthogonalized against the basis in two
+        // full passes (a random vector is not close to the basis, so the
+        // selective test's premise does not hold for it)
+        launch_f1_mask(a, w->f1mask, s);
+        int fresh = 0;
+        CHECKED(count_open(w->f1mask, n_items, &fresh));
+        if (fresh > 0 && j + 1 < w->kq) {
+          LzArgs b = a;
+          b.stopped = w->f1mask;
+          launch_lz_random(b, K, w->R, (uint64_t)(1000 + attempt) * 1000003ull + (uint64_t)j, s, 1);
+          cgs2(b, L, j + 1, nullptr, [](int) {}, 1e300);
+          launch_lz_norms(b, K, w->R, s);
+          launch_lz_scalars(b, K, L.tlo, L.thi, L.m, 3, j, HP.opts.lanczos_tol, brk, 0, s);
+          launch_lz_next(b, K, w->R, Qj(j + 1), s);
+          w->stat_restarts += fresh;
+        }
+        launch_f1_settle(a, s);
+        HIPC(hipGetLastError());
+      }
+      HIPC(hipMemcpyAsync(stop.data(), w->lz_stopped, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(st.data(), w->lz_steps, n_items * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      int bad = 0;
+      for (int i = 0; i < n_items; ++i) bad += (stop[i] == 3);
+      if (bad == 0 || w->pending != DYSON_OK) break;
+      if (attempt == 2) {
+        w->pending = DYSON_EBREAKDOWN;
+        g_err = "Lanczos breakdown persisted after restarts";
+        break;
+      }
+      w->stat_restarts += bad;
+      brk *= 1e-2;
+      launch_lz_reopen(a, K, w->Dl, s);
+      HIPC(hipGetLastError());
+    }
+    if (w->prof.on) launch_prof_collect(a.wctr, n_items, 2, 2, w->d_prof, s);
+    if (w->pending == DYSON_OK) {
+      launch_f1_hpad(a, w->Hm, mm, s);
+      launch_gj_invert(w->Hm, mm, n_items, w->gjC, w->gjR, w->gjQ, s);
+      launch_f1_diag(a, K, w->Vb, V, w->Hm, mm, w->Dl, s);
+      launch_add_into(a, K, w->Dl, w->gacc, s);
+      HIPC(hipGetLastError());
+    }
+    if (steps_out) *steps_out = st;
+    return DYSON_OK;
   }
 
   // One correction level: bilinear Lanczos on X for every (domain, frequency),
@@ -751,7 +875,8 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
         break;
       }
       auto tl = std::chrono::steady_clock::now();
-      st = gr.lanczos_level(l, &lsteps_of[l]);
+      st = P.opts.interface_lanczos ? gr.lanczos_level_iface(l, &lsteps_of[l])
+                                    : gr.lanczos_level(l, &lsteps_of[l]);
       if (verbose) {
         int lmax = 0;
         for (int v : lsteps_of[l]) lmax = std::max(lmax, v);
@@ -941,10 +1066,12 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
       CHECKED(dalloc(&d.tlo, (size_t)L.n_nodes));
       CHECKED(dalloc(&d.thi, (size_t)L.n_nodes));
       CHECKED(dalloc(&d.mcap, (size_t)L.n_nodes));
+      CHECKED(dalloc(&d.m, (size_t)L.n_nodes));
       HIPC(hipMemcpy(d.tile_node, L.tile_node.data(), P.T * sizeof(int), hipMemcpyHostToDevice));
       HIPC(hipMemcpy(d.tlo, L.tile_lo.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
       HIPC(hipMemcpy(d.thi, L.tile_hi.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
       HIPC(hipMemcpy(d.mcap, cap.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
+      HIPC(hipMemcpy(d.m, L.m.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
       p->lv.push_back(d);
     }
     ctx->live_plans.fetch_add(1);
@@ -984,6 +1111,7 @@ dyson_status dyson_plan_destroy(dyson_plan* p) {
       (void)hipFree(d.tlo);
       (void)hipFree(d.thi);
       (void)hipFree(d.mcap);
+      (void)hipFree(d.m);
     }
     (void)hipFree(p->d_nbr);
     (void)hipFree(p->d_kind);
@@ -1101,7 +1229,8 @@ dyson_status dyson_correct_level(dyson_plan* p, int level, int K, const double* 
   launch_to_tile(p->geom, K, d_Gacc, w->gacc, 0.0, s);
   Run run{p, w, K, s};
   std::vector<int> steps;
-  CHECKED(run.lanczos_level(level, &steps));
+  CHECKED(p->hp.opts.interface_lanczos ? run.lanczos_level_iface(level, &steps)
+                                        : run.lanczos_level(level, &steps));
   launch_from_tile(p->geom, K, w->gacc, d_Gacc, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
