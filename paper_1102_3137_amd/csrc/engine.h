@@ -31,6 +31,10 @@ struct DevLevel {
   int* thi = nullptr;
   int* mcap = nullptr;
   int* m = nullptr;     // interface size of each domain
+  int* itiles = nullptr;  // tiles holding interface sites of the level, by domain
+  int* ilo = nullptr;     // [n] range of each domain in itiles
+  int* ihi = nullptr;
+  int n_itiles = 0;
 };
 
 // Event-timed kernel classes (report.kern_*).

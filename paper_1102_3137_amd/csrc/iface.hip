@@ -59,7 +59,8 @@ __global__ __launch_bounds__(256) void k_f1_rhs(LzArgs a, const double* __restri
 }
 
 // s = S p = (H (p - u))|_C with u = B^{-1} E p (zero on C): on the interface
-// sites d p + t (sum of the neighbours' p - u); zero elsewhere.  Also v = p + u.
+// sites d p + t (sum of the neighbours' p - u, p on interface neighbours and
+// u on subdomain ones); zero elsewhere.  Also v = p + u.
 __global__ __launch_bounds__(256) void k_f1_smat(LzArgs a, const double* __restrict__ d,
                                                  const double* __restrict__ p,
                                                  const double* __restrict__ u,
@@ -70,15 +71,18 @@ __global__ __launch_bounds__(256) void k_f1_smat(LzArgs a, const double* __restr
   if (tid >= G.S) return;
   const size_t pp = (size_t)t * G.S + tid;
   cd out = cmk(0.0, 0.0);
-  const cd pv = ld(p, base + tid);
-  if (on_iface(G, pp, a.level)) {
+  // p is read on interface sites only: the vector kernels keep it on the
+  // interface tiles, and other tiles of the buffer hold stale values
+  const bool mine = on_iface(G, pp, a.level);
+  const cd pv = mine ? ld(p, base + tid) : cmk(0.0, 0.0);
+  if (mine) {
     cd acc = cmk(0.0, 0.0);
     for (int dir = 0; dir < 6; ++dir) {
       int nt, nl;
       if (!site_nbr(G, t, tid, dir, nt, nl)) continue;
       const size_t np = (size_t)nt * G.S + nl;
-      if (active(G.kind[np], G.depth[np], a.level))
-        acc = cadd(acc, csub(ld(p, kb + np), ld(u, kb + np)));
+      if (on_iface(G, np, a.level)) acc = cadd(acc, ld(p, kb + np));
+      else if (active(G.kind[np], G.depth[np], a.level)) acc = csub(acc, ld(u, kb + np));
     }
     out = cfma(ld(d, base + tid), pv, cscale(acc, G.t));
   }

@@ -72,8 +72,11 @@ struct LzArgs {
   double* hpart;    // [K*T*hstride] complex
   double* h;        // [K*n_nodes*hstride] complex
   int hstride;
-  const int* tlo;   // [n_nodes] tile range of each domain
+  const int* tlo;   // [n_nodes] tile range of each domain (into tlist when it is set)
   const int* thi;
+  const int* tlist; // tiles the Lanczos vectors live on, grouped by domain, or null
+                    // (every tile of the level); the vector kernels run on these only
+  int n_tlist;
   int n_items;
   unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (CGS update,
                              // CGS products) booked by each item's lead block, or null

@@ -262,8 +262,12 @@ __global__ void k_count_open(const int* __restrict__ done, int n, int* __restric
 // every kernel skip the item (1 exhausted, 2 step cap, 3 breakdown, 4 done
 // in an earlier attempt).
 
+// A tile of the Lanczos vectors: through the level's tile list when it is set.
+__device__ __forceinline__ int lz_tile(const LzArgs& a, int i) { return a.tlist ? a.tlist[i] : i; }
+
 #define LZ_ITEM()                                   \
-  const int t = blockIdx.x, k = blockIdx.y;         \
+  const int ti = blockIdx.x, k = blockIdx.y;        \
+  const int t = lz_tile(a, ti);                     \
   const int node = a.tile_node[t];                  \
   if (node < 0) return;                             \
   const int item = k * a.n_nodes + node;            \
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
+  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])
     a.wctr[(size_t)1 * a.n_items + item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
                                             ((unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
   cd rl[4];
@@ -453,7 +457,7 @@ __global__ void k_cgs_reduce(LzArgs a, int K, const int* __restrict__ tlo,
       cd v[TB];
 #pragma unroll
       for (int q = 0; q < TB; ++q) {
-        const int t = t0 + q < hi ? t0 + q : hi - 1;
+        const int t = lz_tile(a, t0 + q < hi ? t0 + q : hi - 1);
         v[q] = ld(a.hpart + ((size_t)k * a.G.T + t) * (size_t)a.hstride * 2, i);
       }
 #pragma unroll
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
   LZ_ITEM();
   if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
-  if (a.wctr && threadIdx.x == 0 && t == a.tlo[node])
+  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])
     a.wctr[item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
                     ((unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec);
   __shared__ cd hl[1024];
@@ -519,7 +523,8 @@ __global__ void k_cgs_decide(LzArgs a, int K, const int* __restrict__ tlo,
   for (int t0 = lo; t0 < hi; t0 += TB) {
     double v[TB];
 #pragma unroll
-    for (int q = 0; q < TB; ++q) v[q] = a.partial[((size_t)k * a.G.T + (t0 + q < hi ? t0 + q : hi - 1)) * 4];
+    for (int q = 0; q < TB; ++q)
+      v[q] = a.partial[((size_t)k * a.G.T + lz_tile(a, t0 + q < hi ? t0 + q : hi - 1)) * 4];
 #pragma unroll
     for (int q = 0; q < TB; ++q)
       if (t0 + q < hi) r1 += v[q];
@@ -582,7 +587,7 @@ __global__ void k_lz_scalars(LzArgs a, int K, const int* __restrict__ tlo,
     cd v0[TB], v1[TB];
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
-      const size_t qq = ((size_t)k * a.G.T + (t0 + q < hi ? t0 + q : hi - 1)) * per;
+      const size_t qq = ((size_t)k * a.G.T + lz_tile(a, t0 + q < hi ? t0 + q : hi - 1)) * per;
       v0[q] = ld(a.partial, qq);
       v1[q] = per == 2 ? ld(a.partial, qq + 1) : cmk(0.0, 0.0);
     }
@@ -752,6 +757,9 @@ __global__ void k_add_into(LzArgs a, const double* __restrict__ D, double* __res
 
 // ----------------------------------------------------------------- launchers
 static inline dim3 tiles_grid(const TileGeom& G, int K) { return dim3(G.T, K); }
+static inline dim3 lz_grid(const LzArgs& a, int K) {
+  return dim3(a.tlist ? (unsigned)a.n_tlist : (unsigned)a.G.T, K);
+}
 
 void launch_to_tile(const TileGeom& G, int K, const double* nat, double* tile, double fre,
                     hipStream_t s) {
@@ -807,25 +815,25 @@ void launch_freq_keys(const double* omega, int zmode, int K, uint64_t* fkey, hip
 }
 void launch_lz_random(const LzArgs& a, int K, double* q, uint64_t salt, hipStream_t s,
                       int real_only) {
-  k_lz_random<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, salt, real_only);
+  k_lz_random<<<lz_grid(a, K), 256, 0, s>>>(a, q, salt, real_only);
 }
 void launch_lz_scale(const LzArgs& a, int K, double* q, hipStream_t s) {
-  k_lz_scale<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q);
+  k_lz_scale<<<lz_grid(a, K), 256, 0, s>>>(a, q);
 }
 void launch_lz_defect(const LzArgs& a, int K, const double* q, const double* w, double* b,
                       hipStream_t s) {
-  k_lz_defect<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, w, b);
+  k_lz_defect<<<lz_grid(a, K), 256, 0, s>>>(a, q, w, b);
 }
 void launch_lz_alpha(const LzArgs& a, int K, const double* q, const double* u, hipStream_t s) {
-  k_lz_alpha<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, u);
+  k_lz_alpha<<<lz_grid(a, K), 256, 0, s>>>(a, q, u);
 }
 void launch_lz_recur(const LzArgs& a, int K, const double* q, const double* qprev, const double* u,
                      double* r, double* D, hipStream_t s) {
-  k_lz_recur<<<tiles_grid(a.G, K), 256, 0, s>>>(a, q, qprev, u, r, D);
+  k_lz_recur<<<lz_grid(a, K), 256, 0, s>>>(a, q, qprev, u, r, D);
 }
 void launch_cgs_dot(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec,
                     const double* r, int pass, hipStream_t s) {
-  k_cgs_dot<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, pass);
+  k_cgs_dot<<<lz_grid(a, K), 256, 0, s>>>(a, Q, qstride, nvec, r, pass);
 }
 void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec, int pass,
                        hipStream_t s) {
@@ -833,7 +841,7 @@ void launch_cgs_reduce(const LzArgs& a, int K, const int* tlo, const int* thi, i
 }
 void launch_cgs_update(const LzArgs& a, int K, const double* Q, size_t qstride, int nvec, double* r,
                        double* D, int pass, hipStream_t s) {
-  k_cgs_update<<<tiles_grid(a.G, K), 256, 0, s>>>(a, Q, qstride, nvec, r, D, pass);
+  k_cgs_update<<<lz_grid(a, K), 256, 0, s>>>(a, Q, qstride, nvec, r, D, pass);
 }
 void launch_cgs_decide(const LzArgs& a, int K, const int* tlo, const int* thi, int nvec,
                        double eta2, hipStream_t s) {
@@ -841,10 +849,10 @@ void launch_cgs_decide(const LzArgs& a, int K, const int* tlo, const int* thi, i
   k_cgs_decide<<<(n + 127) / 128, 128, 0, s>>>(a, K, tlo, thi, nvec, eta2);
 }
 void launch_lz_norms(const LzArgs& a, int K, const double* r, hipStream_t s) {
-  k_lz_norms<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r);
+  k_lz_norms<<<lz_grid(a, K), 256, 0, s>>>(a, r);
 }
 void launch_lz_next(const LzArgs& a, int K, const double* r, double* qn, hipStream_t s) {
-  k_lz_next<<<tiles_grid(a.G, K), 256, 0, s>>>(a, r, qn);
+  k_lz_next<<<lz_grid(a, K), 256, 0, s>>>(a, r, qn);
 }
 void launch_lz_scalars(const LzArgs& a, int K, const int* tlo, const int* thi, const int* mcap,
                        int op, int j, double tol, double brk, int force, hipStream_t s) {

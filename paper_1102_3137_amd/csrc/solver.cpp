@@ -567,10 +567,10 @@ struct Run {
     const size_t qstride = (size_t)K * P().T * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
       timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, pass, s); });
-      launch_cgs_reduce(a, K, L.tlo, L.thi, nvec, pass, s);
+      launch_cgs_reduce(a, K, a.tlo, a.thi, nvec, pass, s);
       after_reduce(pass);
       timed(2, [&] { launch_cgs_update(a, K, w->Q, qstride, nvec, w->R, D, pass, s); });
-      if (pass == 0) launch_cgs_decide(a, K, L.tlo, L.thi, nvec, eta2, s);
+      if (pass == 0) launch_cgs_decide(a, K, a.tlo, a.thi, nvec, eta2, s);
     }
   }
   void cgs2(const LzArgs& a, const DevLevel& L, int nvec) {
@@ -594,6 +594,12 @@ struct Run {
     launch_zero(w->Dl, V * sizeof(double), s);
     LzArgs a = lz_args(level);
     a.iface = 1;
+    if (L.n_itiles > 0) {  // the vectors live on the interface tiles only
+      a.tlist = L.itiles;
+      a.n_tlist = L.n_itiles;
+      a.tlo = L.ilo;
+      a.thi = L.ihi;
+    }
     const int n_items = K * L.n;
     int mm = 0;
     for (int m : HP.levels[level].m) mm = std::max(mm, m);
@@ -604,7 +610,7 @@ struct Run {
     for (int attempt = 0; attempt < 3; ++attempt) {
       if (attempt > 0) launch_f1_hzero(a, w->Hm, mm, s);
       launch_lz_random(a, K, Qj(0), (uint64_t)attempt, s);
-      launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 0, 0, HP.opts.lanczos_tol, brk, 0, s);
+      launch_lz_scalars(a, K, a.tlo, a.thi, L.m, 0, 0, HP.opts.lanczos_tol, brk, 0, s);
       launch_lz_scale(a, K, Qj(0), s);
       HIPC(hipGetLastError());
       for (int j = 0; j < mm; ++j) {
@@ -618,12 +624,12 @@ struct Run {
         if (w->pending != DYSON_OK) break;
         launch_f1_smat(a, K, w->d, q, w->xB, w->xH, Vj(j), s);   // S p, v = p + u
         launch_lz_alpha(a, K, q, w->xH, s);
-        launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 1, j, HP.opts.lanczos_tol, brk, 0, s);
+        launch_lz_scalars(a, K, a.tlo, a.thi, L.m, 1, j, HP.opts.lanczos_tol, brk, 0, s);
         launch_lz_recur(a, K, q, j > 0 ? Qj(j - 1) : nullptr, w->xH, w->R, nullptr, s);
         cgs2(a, L, j + 1, nullptr, [&](int pass) { launch_f1_hcol(a, w->Hm, mm, j, pass, s); });
         launch_lz_norms(a, K, w->R, s);
         const int force = (HP.opts.fault_step == j + 1 && attempt < HP.opts.fault_attempts);
-        launch_lz_scalars(a, K, L.tlo, L.thi, L.m, 2, j, HP.opts.lanczos_tol, brk, force, s);
+        launch_lz_scalars(a, K, a.tlo, a.thi, L.m, 2, j, HP.opts.lanczos_tol, brk, force, s);
         launch_f1_hcol(a, w->Hm, mm, j, 2, s);
         if (j + 1 < w->kq) launch_lz_next(a, K, w->R, Qj(j + 1), s);
         HIPC(hipGetLastError());
@@ -640,7 +646,7 @@ struct Run {
           launch_lz_random(b, K, w->R, (uint64_t)(1000 + attempt) * 1000003ull + (uint64_t)j, s, 1);
           cgs2(b, L, j + 1, nullptr, [](int) {}, 1e300);
           launch_lz_norms(b, K, w->R, s);
-          launch_lz_scalars(b, K, L.tlo, L.thi, L.m, 3, j, HP.opts.lanczos_tol, brk, 0, s);
+          launch_lz_scalars(b, K, a.tlo, a.thi, L.m, 3, j, HP.opts.lanczos_tol, brk, 0, s);
           launch_lz_next(b, K, w->R, Qj(j + 1), s);
           w->stat_restarts += fresh;
         }
@@ -1057,9 +1063,33 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
     HIPC(hipMemcpy(p->d_depth, P.depth.data(), TS, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(p->d_site_of, P.site_of.data(), TS * sizeof(int), hipMemcpyHostToDevice));
     HIPC(hipMemcpy(p->d_pos_of, P.pos_of.data(), (size_t)P.N * sizeof(int), hipMemcpyHostToDevice));
-    for (const auto& L : P.levels) {
+    for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+      const auto& L = P.levels[lev];
       DevLevel d;
       d.n = L.n_nodes;
+      // tiles that hold interface sites of the level, grouped by domain: the
+      // interface form's Lanczos vectors vanish on every other tile
+      std::vector<int> itl, ilo(L.n_nodes), ihi(L.n_nodes);
+      for (int nd = 0; nd < L.n_nodes; ++nd) {
+        ilo[nd] = (int)itl.size();
+        for (int t = L.tile_lo[nd]; t < L.tile_hi[nd]; ++t) {
+          bool has = false;
+          for (int q = 0; q < P.S && !has; ++q) {
+            const size_t pos = (size_t)t * P.S + q;
+            has = P.kind[pos] == KIND_SEP && P.depth[pos] == (int)lev;
+          }
+          if (has) itl.push_back(t);
+        }
+        ihi[nd] = (int)itl.size();
+      }
+      d.n_itiles = (int)itl.size();
+      CHECKED(dalloc(&d.itiles, std::max<size_t>(itl.size(), 1)));
+      CHECKED(dalloc(&d.ilo, (size_t)L.n_nodes));
+      CHECKED(dalloc(&d.ihi, (size_t)L.n_nodes));
+      if (!itl.empty())
+        HIPC(hipMemcpy(d.itiles, itl.data(), itl.size() * sizeof(int), hipMemcpyHostToDevice));
+      HIPC(hipMemcpy(d.ilo, ilo.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
+      HIPC(hipMemcpy(d.ihi, ihi.data(), L.n_nodes * sizeof(int), hipMemcpyHostToDevice));
       std::vector<int> cap(L.n_nodes);
       for (int i = 0; i < L.n_nodes; ++i) cap[i] = step_cap(L.m[i], o);
       CHECKED(dalloc(&d.tile_node, (size_t)P.T));
@@ -1112,6 +1142,9 @@ dyson_status dyson_plan_destroy(dyson_plan* p) {
       (void)hipFree(d.thi);
       (void)hipFree(d.mcap);
       (void)hipFree(d.m);
+      (void)hipFree(d.itiles);
+      (void)hipFree(d.ilo);
+      (void)hipFree(d.ihi);
     }
     (void)hipFree(p->d_nbr);
     (void)hipFree(p->d_kind);
