@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -35,18 +37,29 @@ struct Unit {
   bool ok;
 };
 
-__device__ __forceinline__ Unit decode(const CocgLaunch& a) {
+// Units of a launch: (frequency slot, tile) pairs, the slot taken through
+// the compacted list of open frequencies when there is one.
+__device__ __forceinline__ int n_units(const CocgLaunch& a) {
+  return (a.klist ? *a.kcount : a.K) * a.G.T;
+}
+__device__ __forceinline__ Unit decode_id(const CocgLaunch& a, int id, int n) {
   Unit u;
   u.wave = threadIdx.x >> 6;
   u.lane = threadIdx.x & 63;
-  const int id = blockIdx.x * WAVES + u.wave;
-  u.ok = id < a.K * a.G.T;
-  u.k = u.ok ? id / a.G.T : 0;
+  u.ok = id < n;
+  const int ks = u.ok ? id / a.G.T : 0;
+  u.k = u.ok ? (a.klist ? a.klist[ks] : ks) : 0;
   u.t = u.ok ? id % a.G.T : 0;
   u.node = u.ok ? a.tile_node[u.t] : -1;
   u.item = u.k * a.n_nodes + u.node;
   u.ok = u.ok && u.node >= 0;
   return u;
+}
+// every unit, one per wave (the initialisation: no list)
+__device__ __forceinline__ Unit decode(const CocgLaunch& a) {
+  CocgLaunch b = a;
+  b.klist = nullptr;
+  return decode_id(b, blockIdx.x * WAVES + (threadIdx.x >> 6), a.K * a.G.T);
 }
 
 // Sum over the item's tiles of `per` complex partials per unit, fixed order:
@@ -352,8 +365,7 @@ __device__ __forceinline__ int halo_site(const TileGeom& G, int h, int& dir) {
 // tile), whose p_new = z + beta p_old is formed here as for the own sites
 // (the neighbour tile, when active, belongs to the same domain and so to
 // the same item and beta).
-__global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
-  const Unit u = decode(a);
+__device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const Unit& u) {
   if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
@@ -420,6 +432,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
     beta = cdiv(rho, rho_prev);
     if (lead && u.lane == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
   }
+  if (lead && u.lane == 0) a.kalive[u.k] = it + 2;  // the item stays open
   // profiling: the item's lead wave books the algorithmic bytes of all the
   // item's units (one writer per item and launch: no atomics)
   if (a.wctr && lead && u.lane == 0)
@@ -472,6 +485,13 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
   if (u.lane == 0) st(a.partS, (size_t)u.k * G.T + u.t, mu);
 }
 
+// Wave w of workgroup b takes unit b * WAVES + w of the launch's list; the
+// grid covers every unit, and the waves past the list's end leave at once.
+__global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
+  const int n = n_units(a);
+  stencil_unit(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6), n));
+}
+
 // r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z, |r|^2 ; converged
 // when |r|^2 <= tol^2 |b|^2, else beta = rho'/rho.  x += alpha p is applied
 // every other iteration: on odd iterations x += alpha_{i-1} p_{i-1} + alpha_i
@@ -479,8 +499,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
 // the next; the stencil launch that finds an item converged after an even
 // iteration applies the pending alpha_{i-1} p_{i-1}.
 template <typename F, bool REG>
-__device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
-  const Unit u = decode(a);
+__device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, const Unit& u) {
   if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
@@ -613,6 +632,12 @@ __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
 }
 
 template <typename F, bool REG>
+__device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
+  const int n = n_units(a);
+  cocg_update_unit<F, REG>(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6), n));
+}
+
+template <typename F, bool REG>
 __global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
   cocg_update_body<F, REG>(a, it);
 }
@@ -742,17 +767,9 @@ __device__ __forceinline__ void plane_tile_solve(const PlaneFactor<F>& f, const 
 
 // Unit of a workgroup-per-unit launch (uniform over the workgroup).
 __device__ __forceinline__ Unit decode_wg(const CocgLaunch& a) {
-  Unit u;
-  u.wave = threadIdx.x >> 6;
-  u.lane = threadIdx.x & 63;
-  const int id = blockIdx.x;
-  u.ok = id < a.K * a.G.T;
-  u.k = u.ok ? id / a.G.T : 0;
-  u.t = u.ok ? id % a.G.T : 0;
-  u.node = u.ok ? a.tile_node[u.t] : -1;
-  u.item = u.k * a.n_nodes + u.node;
-  u.ok = u.ok && u.node >= 0;
-  return u;
+  CocgLaunch b = a;
+  b.klist = nullptr;
+  return decode_id(b, blockIdx.x, a.K * a.G.T);
 }
 
 template <typename F>
@@ -800,8 +817,7 @@ __global__ __launch_bounds__(256) void k_cocg_init_planes(CocgLaunch a,
 
 // The stencil launch of k_cocg_stencil, one thread per site and one halo
 // slot per thread (6 s^2 <= 216 slots).
-__global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
-  const Unit u = decode_wg(a);
+__device__ __forceinline__ void stencil_planes_unit(const CocgLaunch& a, int it, const Unit& u) {
   if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
@@ -844,6 +860,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
     beta = cdiv(rho, rho_prev);
     if (lead && threadIdx.x == 0) st(a.rho2 + (size_t)(it & 1) * a.n_items * 2, u.item, rho);
   }
+  if (lead && threadIdx.x == 0) a.kalive[u.k] = it + 2;  // the item stays open
   if (a.wctr && lead && threadIdx.x == 0)
     a.wctr[(size_t)1 * a.n_items + u.item] +=
         (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
@@ -880,9 +897,13 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
   if (threadIdx.x == 0) st(a.partS, (size_t)u.k * G.T + u.t, mu);
 }
 
+// A workgroup per unit of the launch's list (the grid covers every unit).
+__global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
+  stencil_planes_unit(a, it, decode_id(a, blockIdx.x, n_units(a)));
+}
+
 template <typename F>
-__global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it) {
-  const Unit u = decode_wg(a);
+__device__ __forceinline__ void update_planes_unit(const CocgLaunch& a, int it, const Unit& u) {
   if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
@@ -944,6 +965,11 @@ __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it
        cfma(alpha, ld(a.p_new, base + l), cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l))));
 }
 
+template <typename F>
+__global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it) {
+  update_planes_unit<F>(a, it, decode_id(a, blockIdx.x, n_units(a)));
+}
+
 // Convergence bookkeeping after launch `it` (it = 0 follows the
 // initialisation) and the number of items still open, added into *open
 // (zeroed by the launcher).  One wave per item, reducing the item's partials
@@ -967,6 +993,7 @@ __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* _
           st(a.rho2, item, s0);
           a.st.iters[item] = 0;
           a.st.done[item] = (s1.x > 0.0) ? 0 : 1;
+          if (s1.x > 0.0) a.kalive[k] = 1;
         }
         mine = s1.x > 0.0;
       } else {
@@ -982,6 +1009,38 @@ __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* _
     const int c = cnt[0] + cnt[1] + cnt[2] + cnt[3];
     if (c) atomicAdd(open, c);
   }
+}
+
+// The frequencies whose stamp says they still have an open item, in
+// increasing order, and their number: the unit list of the following
+// stencil and update launches.  One workgroup; a block-wide prefix count.
+__global__ __launch_bounds__(1024) void k_cocg_compact(CocgLaunch a, int stamp,
+                                                       int* __restrict__ klist,
+                                                       int* __restrict__ kcount) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < a.K; k0 += 1024) {
+    const int k = k0 + threadIdx.x;
+    const bool live = k < a.K && a.kalive[k] == stamp;
+    const unsigned long long m = __ballot(live);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    if (live) klist[off + before] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int i = 0; i < 16; ++i) tot += wsum[i];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *kcount = base;
 }
 
 // profiling: fold per-item byte counts [classes][n] into tot[class], zeroing them
@@ -1016,6 +1075,7 @@ static inline unsigned planes_blocks(const CocgLaunch& L) {
   return (unsigned)((size_t)L.K * L.G.T);
 }
 
+
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
   if (L.G.sx > 16) {  // plane slices: a workgroup per unit
     if (L.fp16) k_cocg_init_planes<__half><<<planes_blocks(L), 256, 0, s>>>(L, b);
@@ -1032,6 +1092,9 @@ void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s) {
   if (L.G.sx > 16) k_cocg_stencil_planes<<<planes_blocks(L), 256, 0, s>>>(L, it);
   else k_cocg_stencil<<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
 }
+void launch_cocg_compact(const CocgLaunch& L, int stamp, int* klist, int* kcount, hipStream_t s) {
+  k_cocg_compact<<<1, 1024, 0, s>>>(L, stamp, klist, kcount);
+}
 void launch_prof_collect(unsigned long long* per_item, int n, int classes, int first_class,
                          unsigned long long* tot, hipStream_t s) {
   k_prof_collect<<<1, 256, 0, s>>>(per_item, n, classes, first_class, tot);
@@ -1042,14 +1105,16 @@ void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s) {
 }
 void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
   if (L.G.sx > 16) {
-    if (L.fp16) k_cocg_update_planes<__half><<<planes_blocks(L), 256, 0, s>>>(L, it);
-    else if (L.fp32) k_cocg_update_planes<float><<<planes_blocks(L), 256, 0, s>>>(L, it);
-    else k_cocg_update_planes<double><<<planes_blocks(L), 256, 0, s>>>(L, it);
+    const unsigned nb = planes_blocks(L);
+    if (L.fp16) k_cocg_update_planes<__half><<<nb, 256, 0, s>>>(L, it);
+    else if (L.fp32) k_cocg_update_planes<float><<<nb, 256, 0, s>>>(L, it);
+    else k_cocg_update_planes<double><<<nb, 256, 0, s>>>(L, it);
     return;
   }
-  if (L.fp16) k_cocg_update<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
-  else if (L.fp32) k_cocg_update_occ3<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
-  else k_cocg_update<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, it);
+  const unsigned nb = cocg_blocks(L);
+  if (L.fp16) k_cocg_update<__half, true><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  else if (L.fp32) k_cocg_update_occ3<float, true><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  else k_cocg_update<double, false><<<nb, 64 * WAVES, 0, s>>>(L, it);
 }
 
 }  // namespace dyson

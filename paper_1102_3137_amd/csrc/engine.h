@@ -74,6 +74,7 @@ struct Work {
   // projected Hessenberg matrices (one per item) and the inversion's scratch
   double *Vb = nullptr, *Hm = nullptr, *gjC = nullptr, *gjR = nullptr, *gjQ = nullptr;
   int* f1mask = nullptr;  // skip array of the fresh-direction continuation
+  int *klist = nullptr, *kalive = nullptr, *d_kcount = nullptr;  // inner solves' open frequencies
   double *lz_alpha = nullptr, *lz_beta = nullptr, *lz_unorm2 = nullptr, *lz_umax2 = nullptr,
          *lz_scal = nullptr;
   int* d_count = nullptr;

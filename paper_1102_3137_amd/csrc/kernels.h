@@ -52,6 +52,12 @@ struct CocgLaunch {
                          // updated every other iteration, alpha_{i-1} p_{i-1} + alpha_i p_i)
   double tol2;           // squared relative residual target
   int flush;             // final stencil launch: close every open item
+  const int* klist;      // frequencies with an open item (compacted), or null: every
+                         // frequency; the stencil and update launches loop over
+                         // the units of these only (persistent grid)
+  const int* kcount;     // [1] length of klist
+  int* kalive;           // [K] stamp of the last launch after which frequency k still
+                         // had an open item (1: the initial check, it + 2: stencil it)
 };
 
 struct LzArgs {
@@ -109,6 +115,7 @@ void launch_factor_diag(const TileGeom& G, int K, const double* d, double* fac64
 
 void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s);
 void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s);
+void launch_cocg_compact(const CocgLaunch& L, int stamp, int* klist, int* kcount, hipStream_t s);
 void launch_cocg_check(const CocgLaunch& L, int it, int* open, hipStream_t s);
 void launch_prof_collect(unsigned long long* per_item, int n, int classes, int first_class,
                          unsigned long long* tot, hipStream_t s);

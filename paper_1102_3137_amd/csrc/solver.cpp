@@ -133,6 +133,8 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
       {(void**)&w->cst.bn2, ni * 8},   {(void**)&w->rho2, ni * 32},
       {(void**)&w->alph, ni * 16},
       {(void**)&w->partS, (size_t)K * P.T * 16},
+      {(void**)&w->klist, (size_t)K * 4}, {(void**)&w->kalive, (size_t)K * 4},
+      {(void**)&w->d_kcount, 16},
       {(void**)&w->lz_stopped, ni * 4}, {(void**)&w->lz_steps, ni * 4},
       {(void**)&w->lz_reorth, ni * 4}, {(void**)&w->lz_armed, ni * 4},
       {(void**)&w->lz_alpha, ni * 16},  {(void**)&w->lz_beta, ni * 16},
@@ -472,13 +474,22 @@ struct Run {
     c.tol2 = HP.opts.inner_tol * HP.opts.inner_tol;
     const int slot = 2 * level + (g == level ? 0 : 1);
     if ((int)w->pred.size() <= slot) w->pred.resize(slot + 1, 0);
+    // the stencil and update launches run over the frequencies that still
+    // have an open item (stamped by the check and the stencil, compacted
+    // after each)
+    c.kalive = w->kalive;
+    launch_zero(w->kalive, (size_t)K * sizeof(int), s);
     launch_cocg_init(c, b, s);
     launch_cocg_check(c, 0, w->d_count, s);
+    launch_cocg_compact(c, 1, w->klist, w->d_kcount, s);
+    c.klist = w->klist;
+    c.kcount = w->d_kcount;
     const int maxit = HP.opts.max_inner_iters;
     int it = 0, open = 1;
     int check_at = std::max(1, w->pred[slot] - 1);
     while (it < maxit) {
       timed(1, [&] { launch_cocg_stencil(c, it, s); });
+      launch_cocg_compact(c, it + 2, w->klist, w->d_kcount, s);
       timed(0, [&] { launch_cocg_update(c, it, s); });
       std::swap(c.p_old, c.p_new);
       ++it;
