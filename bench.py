@@ -6,11 +6,16 @@ frequencies at beta = 20, 16x16 subdomain tiles, recursive bisection,
 Lanczos to full interface rank (truncated ranks do not reach 1e-6).
 One step = one dyson_solve over all 64 frequencies: assembly, subdomain
 factorization and diag(B^{-1}), eight correction levels of bilinear Lanczos
-with inner solves, combine and scatter.  Inputs are resident in HBM before
-the timed region.  The inner solves stop at relative residual 1e-11, which
-keeps the result about 1e-9 from the oracle (checked on 16 frequencies spread
-over the range, and by the solve's own direct solves at two sites of every
-frequency); only results within 1e-6 count.
+with inner solves, combine and scatter.  The correction runs in the
+interface form by default (Lanczos on the Schur complement of each domain,
+one inner solve per step, derived from eqs. (5)-(7)); --form x times the
+X form of eqs. (8)-(12) (two inner solves per step), and the line carries
+the other form's one-solve figure beside the step's.  Inputs are resident
+in HBM before the timed region.  The inner solves stop at relative residual
+1e-11, which keeps the result 1e-10 (interface form) to 2e-9 (X form) from
+the oracle (checked on 16 frequencies spread over the range, and by the
+solve's own direct solves at two sites of every frequency); only results
+within 1e-6 count.
 
 Prints one JSON line.  Diagnostics go to stderr.
 """
@@ -574,10 +579,10 @@ def main():
     ap.add_argument("--no-standalone", action="store_true",
                     help="skip the untimed solve that times the dominant kernel with the "
                          "levels in sequence")
-    ap.add_argument("--interface", action="store_true",
-                    help="time the interface form of the correction (Lanczos on the Schur "
-                         "complement, one inner solve per step) as the step")
-    ap.add_argument("--no-iface", action="store_true",
+    ap.add_argument("--form", choices=["interface", "x"], default="interface",
+                    help="form of the correction the step times: Lanczos on the Schur "
+                         "complement (one inner solve per step) or on X (eqs. (8)-(12))")
+    ap.add_argument("--no-other-form", action="store_true",
                     help="skip the one-solve comparison with the other form of the correction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=16)
@@ -673,7 +678,7 @@ def main():
     tom = torch.from_numpy(om).to(dev)
     tsig = torch.from_numpy(np.ascontiguousarray(sig)).to(dev)
     G = torch.empty((w.n_freq, w.n_sites), dtype=torch.complex128, device=dev)
-    iface = 1 if args.interface else 0
+    iface = 1 if args.form == "interface" else 0
     plan = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                 inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
                 profile=0 if args.no_profile else 1, level_streams=args.level_streams,
@@ -862,7 +867,7 @@ def main():
     # then one measured): the X form of eqs. (8)-(12) against Lanczos on the
     # Schur complement, whose diag(X) agrees at full interface rank
     other = None
-    if not args.no_iface:
+    if not args.no_other_form:
         po = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
                   level_streams=args.level_streams, interface_lanczos=1 - iface)

@@ -142,6 +142,14 @@ typedef struct {
                          projected Hessenberg matrix H inverted once per (domain,
                          frequency) and diag(X) = diag(V H^{-1} V^T) with
                          V = [B^{-1} E P; P] [0] */
+  int inner_graphs;     /* the inner solves' iterations between convergence polls
+                         go to the GPU as captured HIP graphs of 8 iterations
+                         (stencil, open-frequency compaction and update launches),
+                         replayed for every later solve of the same shape; the
+                         results are bit for bit those of direct launches.
+                         0 = default (on), 1 = on, -1 = off (every kernel
+                         launched directly).  Off while profiling and in
+                         dyson_solve_noalloc [0] */
 } dyson_opts;
 
 /* Filled by dyson_solve when report != NULL. */

@@ -40,7 +40,8 @@ class Opts(C.Structure):
                 ("inner_tol", C.c_double), ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
                 ("profile", C.c_int), ("level_streams", C.c_int), ("check_sites", C.c_int),
                 ("fault_step", C.c_int), ("fault_attempts", C.c_int),
-                ("breakdown_tol", C.c_double), ("interface_lanczos", C.c_int)]
+                ("breakdown_tol", C.c_double), ("interface_lanczos", C.c_int),
+                ("inner_graphs", C.c_int)]
 
 
 class Report(C.Structure):
@@ -308,7 +309,7 @@ class Plan:
                  inner_tol=1e-14, lanczos_tol=1e-11, seed=0x5EED, profile=False, device=0,
                  ctx: "Context | None" = None, level_streams=4, periodic=None,
                  check_sites=2, fault_step=0, fault_attempts=0, breakdown_tol=1e-4,
-                 interface_lanczos=0):
+                 interface_lanczos=0, inner_graphs=0):
         dims = tuple(int(x) for x in dims)
         lat = Lattice()
         lat.dim = len(dims)
@@ -320,7 +321,7 @@ class Plan:
         o = Opts(leaf_edge, partition, precision, max_rank, extra_steps, max_inner_iters,
                  inner_tol, lanczos_tol, seed, int(profile), int(level_streams),
                  int(check_sites) if check_sites else -1, int(fault_step), int(fault_attempts),
-                 float(breakdown_tol), int(interface_lanczos))
+                 float(breakdown_tol), int(interface_lanczos), int(inner_graphs))
         self.dims = dims
         self.n_sites = 1
         for x in dims:

@@ -39,27 +39,31 @@ struct Unit {
 
 // Units of a launch: (frequency slot, tile) pairs, the slot taken through
 // the compacted list of open frequencies when there is one.
-__device__ __forceinline__ int n_units(const CocgLaunch& a) {
-  return (a.klist ? *a.kcount : a.K) * a.G.T;
-}
-__device__ __forceinline__ Unit decode_id(const CocgLaunch& a, int id, int n) {
+// The list length, the list entry and the tile's domain are read together
+// (the entry and the tile through a clamped, always valid unit index), so a
+// unit's first memory round trip yields all three.
+__device__ __forceinline__ Unit decode_id(const CocgLaunch& a, int id) {
   Unit u;
   u.wave = threadIdx.x >> 6;
   u.lane = threadIdx.x & 63;
-  u.ok = id < n;
-  const int ks = u.ok ? id / a.G.T : 0;
-  u.k = u.ok ? (a.klist ? a.klist[ks] : ks) : 0;
-  u.t = u.ok ? id % a.G.T : 0;
-  u.node = u.ok ? a.tile_node[u.t] : -1;
+  const int kt = a.K * a.G.T;
+  const int idc = id < kt ? id : kt - 1;
+  const int ks = idc / a.G.T;
+  u.t = idc - ks * a.G.T;
+  const int nk = a.klist ? *a.kcount : a.K;
+  const int kk = a.klist ? a.klist[ks] : ks;
+  const int node = a.tile_node[u.t];
+  u.ok = id < nk * a.G.T && node >= 0;
+  u.k = u.ok ? kk : 0;
+  u.node = u.ok ? node : -1;
   u.item = u.k * a.n_nodes + u.node;
-  u.ok = u.ok && u.node >= 0;
   return u;
 }
 // every unit, one per wave (the initialisation: no list)
 __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
   CocgLaunch b = a;
   b.klist = nullptr;
-  return decode_id(b, blockIdx.x * WAVES + (threadIdx.x >> 6), a.K * a.G.T);
+  return decode_id(b, blockIdx.x * WAVES + (threadIdx.x >> 6));
 }
 
 // Sum over the item's tiles of `per` complex partials per unit, fixed order:
@@ -67,9 +71,9 @@ __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
 // loads of a chunk of CH tiles per lane go out together (addresses clamped to
 // the range, so every load is valid) and are added in order afterwards: one
 // memory round trip per chunk instead of one per tile.
+template <int CH = 2>
 __device__ __forceinline__ void item_sum_of(const double* part, int per, const CocgLaunch& a,
                                             int k, int node, int lane, cd& s0, cd& s1) {
-  constexpr int CH = 2;
   const int lo = a.tlo[node], hi = a.thi[node];
   s0 = cmk(0.0, 0.0);
   s1 = cmk(0.0, 0.0);
@@ -93,9 +97,10 @@ __device__ __forceinline__ void item_sum_of(const double* part, int per, const C
   s0 = wave_sum(s0);
   if (per == 2) s1 = wave_sum(s1);
 }
+template <int CH = 2>
 __device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
                                          const Unit& u, cd& s0, cd& s1) {
-  item_sum_of(part, per, a, u.k, u.node, u.lane, s0, s1);
+  item_sum_of<CH>(part, per, a, u.k, u.node, u.lane, s0, s1);
 }
 
 // ---------------------------------------------------------- tile solve
@@ -366,7 +371,10 @@ __device__ __forceinline__ int halo_site(const TileGeom& G, int h, int& dir) {
 // (the neighbour tile, when active, belongs to the same domain and so to
 // the same item and beta).
 __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
+  if (!u.ok) return;
+  // the item state goes out with the unit's data (a unit of a closed item
+  // then leaves with its loads unused)
+  const int state = a.st.done[u.item];
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)u.k * NP;
@@ -408,12 +416,13 @@ __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const 
     hpo[j] = ld(a.p_old, kb + hi_[j]);
     hz[j] = ld(a.z, kb + hi_[j]);
   }
+  if (!open_here(state, stencil_mark(it))) return;
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
     const double bn2 = a.st.bn2[u.item];
     const cd rho_prev = ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item);
     cd rho, rr;
-    item_sum(a.partU, 2, a, u, rho, rr);
+    item_sum<4>(a.partU, 2, a, u, rho, rr);
     if (a.flush || rr.x <= a.tol2 * bn2) {
       if (it & 1) {  // the last update was even: x still lacks alpha_{i-1} p_{i-1}
         const cd ap = ld(a.alph, u.item);
@@ -488,8 +497,7 @@ __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const 
 // Wave w of workgroup b takes unit b * WAVES + w of the launch's list; the
 // grid covers every unit, and the waves past the list's end leave at once.
 __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
-  const int n = n_units(a);
-  stencil_unit(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6), n));
+  stencil_unit(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6)));
 }
 
 // r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z, |r|^2 ; converged
@@ -500,7 +508,8 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
 // iteration applies the pending alpha_{i-1} p_{i-1}.
 template <typename F, bool REG>
 __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
+  if (!u.ok) return;
+  const int state = a.st.done[u.item];  // checked once the unit's loads are out
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   const F* fac = (const F*)a.fac;
@@ -541,6 +550,10 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
   if constexpr (kEarly) load_item_state();
   WaveFactor<F, REG> f;
   f.load(fac, fbase, G.sx, G.sy, u.lane);
+  if (!open_here(state, update_mark(it))) {
+    wait_vm_all();  // the LDS copies land before the wave leaves
+    return;
+  }
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if constexpr (!kEarly) load_item_state();
@@ -633,8 +646,7 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
 
 template <typename F, bool REG>
 __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
-  const int n = n_units(a);
-  cocg_update_unit<F, REG>(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6), n));
+  cocg_update_unit<F, REG>(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6)));
 }
 
 template <typename F, bool REG>
@@ -769,7 +781,7 @@ __device__ __forceinline__ void plane_tile_solve(const PlaneFactor<F>& f, const 
 __device__ __forceinline__ Unit decode_wg(const CocgLaunch& a) {
   CocgLaunch b = a;
   b.klist = nullptr;
-  return decode_id(b, blockIdx.x, a.K * a.G.T);
+  return decode_id(b, blockIdx.x);
 }
 
 template <typename F>
@@ -899,7 +911,7 @@ __device__ __forceinline__ void stencil_planes_unit(const CocgLaunch& a, int it,
 
 // A workgroup per unit of the launch's list (the grid covers every unit).
 __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int it) {
-  stencil_planes_unit(a, it, decode_id(a, blockIdx.x, n_units(a)));
+  stencil_planes_unit(a, it, decode_id(a, blockIdx.x));
 }
 
 template <typename F>
@@ -967,7 +979,7 @@ __device__ __forceinline__ void update_planes_unit(const CocgLaunch& a, int it, 
 
 template <typename F>
 __global__ __launch_bounds__(256) void k_cocg_update_planes(CocgLaunch a, int it) {
-  update_planes_unit<F>(a, it, decode_id(a, blockIdx.x, n_units(a)));
+  update_planes_unit<F>(a, it, decode_id(a, blockIdx.x));
 }
 
 // Convergence bookkeeping after launch `it` (it = 0 follows the

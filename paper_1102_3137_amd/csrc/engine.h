@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -83,6 +84,10 @@ struct Work {
   double* partS = nullptr;  // inner solves: per-unit p^T A p
   double* stage_om = nullptr;  // [2*Kcap] staging of host-side frequencies
   std::vector<int> pred;    // predicted inner iterations per (level, graph) for polling
+  // captured chunks of inner iterations, keyed by the launch arguments and
+  // the first iteration; replayed on this Work's stream
+  std::unordered_map<std::string, hipGraphExec_t> graphs;
+  bool graphs_broken = false;  // a capture failed: direct launches from then on
   int* h_count = nullptr;   // pinned (h_static for a carved Work)
   // carved: the buffers are slices of a caller-provided region (the
   // allocation-free entry point); nothing is freed, no profiling events are

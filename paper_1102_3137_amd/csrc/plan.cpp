@@ -48,6 +48,7 @@ dyson_opts merge_opts(const dyson_opts* u) {
   o.fault_attempts = u->fault_attempts;
   if (u->breakdown_tol > 0) o.breakdown_tol = u->breakdown_tol;
   o.interface_lanczos = u->interface_lanczos;
+  o.inner_graphs = u->inner_graphs;
   return o;
 }
 
@@ -88,6 +89,7 @@ std::string build_plan(const dyson_lattice& lat, const dyson_opts& opts, HostPla
     return "breakdown_tol must be in (0, 1)";
   if (opts.interface_lanczos != 0 && opts.interface_lanczos != 1)
     return "interface_lanczos must be 0 or 1";
+  if (opts.inner_graphs < -1 || opts.inner_graphs > 1) return "inner_graphs must be -1, 0 or 1";
   if (opts.interface_lanczos && opts.max_rank > 0)
     return "the interface form runs to full rank (max_rank must be 0)";
   long long n = (long long)lat.L[0] * lat.L[1] * lat.L[2];

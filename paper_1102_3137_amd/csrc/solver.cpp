@@ -307,6 +307,9 @@ void free_work(Work* w, hipStream_t s) {
   w->plan = nullptr;
   w->fac_g[0] = w->fac_g[1] = -1000;
   w->pred.clear();
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  w->graphs_broken = false;
 }
 
 namespace {
@@ -441,11 +444,55 @@ struct Run {
   // COCG on graph g for every item of `level`, x = A_g^{-1} b.  Two launches
   // per iteration; the host polls the device's open-item count only near the
   // iteration count the previous solve of the same kind needed.
+  // Iterations [it0, it0 + n) of an inner solve: stencil, open-frequency
+  // compaction and update per iteration (p_old and p_new trade places).
+  void launch_iterations(CocgLaunch c, int it0, int n) {
+    for (int i = 0; i < n; ++i) {
+      timed(1, [&] { launch_cocg_stencil(c, it0 + i, s); });
+      launch_cocg_compact(c, it0 + i + 2, w->klist, w->d_kcount, s);
+      timed(0, [&] { launch_cocg_update(c, it0 + i, s); });
+      std::swap(c.p_old, c.p_new);
+    }
+  }
+
+  // The same iterations as one captured HIP graph, made on first use and
+  // replayed for every later solve with the same launch arguments (the
+  // buffers of a Work do not move between calls).  false: not available
+  // (the caller launches directly).
+  bool replay_iterations(const CocgLaunch& c, int it0, int n) {
+    if (w->graphs_broken) return false;
+    std::string key(reinterpret_cast<const char*>(&c), sizeof(c));
+    key.append(reinterpret_cast<const char*>(&it0), sizeof(it0));
+    key.append(reinterpret_cast<const char*>(&n), sizeof(n));
+    auto f = w->graphs.find(key);
+    if (f == w->graphs.end()) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        w->graphs_broken = true;
+        return false;
+      }
+      launch_iterations(c, it0, n);
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ge = nullptr;
+      const bool ok = hipStreamEndCapture(s, &gr) == hipSuccess && gr &&
+                      hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0) == hipSuccess;
+      if (gr) (void)hipGraphDestroy(gr);
+      if (!ok) {
+        (void)hipGetLastError();
+        w->graphs_broken = true;
+        return false;
+      }
+      f = w->graphs.emplace(std::move(key), ge).first;
+    }
+    return hipGraphLaunch(f->second, s) == hipSuccess;
+  }
+
   dyson_status cocg(int level, int g, const void* fac, const double* b, double* x,
                     bool skip_stopped = true) {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
-    CocgLaunch c{};
+    CocgLaunch c;
+    std::memset(&c, 0, sizeof(c));  // padding included: the struct keys the graph cache
     c.G = p->geom;
     c.K = K;
     c.g = g;
@@ -487,12 +534,19 @@ struct Run {
     const int maxit = HP.opts.max_inner_iters;
     int it = 0, open = 1;
     int check_at = std::max(1, w->pred[slot] - 1);
+    // iterations before the first poll go in chunks of kChunk (an even
+    // count: p_old and p_new end where they started) as captured graphs
+    constexpr int kChunk = 8;
+    const bool graphs = HP.opts.inner_graphs >= 0 && !w->prof.on && !w->carved;
     while (it < maxit) {
-      timed(1, [&] { launch_cocg_stencil(c, it, s); });
-      launch_cocg_compact(c, it + 2, w->klist, w->d_kcount, s);
-      timed(0, [&] { launch_cocg_update(c, it, s); });
-      std::swap(c.p_old, c.p_new);
-      ++it;
+      const int stop = std::min(check_at, maxit);
+      if (graphs && it + kChunk <= stop && replay_iterations(c, it, kChunk)) {
+        it += kChunk;
+      } else {
+        launch_iterations(c, it, 1);
+        std::swap(c.p_old, c.p_new);
+        ++it;
+      }
       if (it >= check_at || it == maxit) {
         launch_cocg_check(c, it, w->d_count, s);
         HIPC(hipMemcpyAsync(w->h_count, w->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
