@@ -54,12 +54,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload, precision):
+def traffic_for(kernel, workload, precision, form):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (profiles/<kernel>_<workload>_<precision>.txt: FETCH_SIZE and
-    WRITE_SIZE per dispatch, scaled by a plain-copy calibration), if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}.txt")
+    summary (profiles/<kernel>_<workload>_<precision>_<form>.txt: FETCH_SIZE
+    and WRITE_SIZE per dispatch, scaled by a plain-copy calibration), if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_{form}.txt")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -718,7 +718,7 @@ def main():
     roof = None
     if not args.no_profile:
         c = 0
-        tr = traffic_for(KERNEL_NAMES[c], args.workload, args.precision)
+        tr = traffic_for(KERNEL_NAMES[c], args.workload, args.precision, args.form)
         pe = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=1,
                   level_streams=args.level_streams, interface_lanczos=iface)

@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -38,15 +39,16 @@ def test_oracle_sample_spans_the_frequency_range():
         assert oracle.rel_err(g, dense) < 1e-12
 
 
-def test_traffic_is_reported_only_for_the_profiled_source(monkeypatch):
-    t = bench.traffic_for("k_cocg_update", "square256", "mixed16")
-    path = os.path.join(ROOT, "profiles", "k_cocg_update_square256_mixed16.txt")
+@pytest.mark.parametrize("form", ["interface", "x"])
+def test_traffic_is_reported_only_for_the_profiled_source(monkeypatch, form):
+    t = bench.traffic_for("k_cocg_update", "square256", "mixed16", form)
+    path = os.path.join(ROOT, "profiles", f"k_cocg_update_square256_mixed16_{form}.txt")
     fields = dict(ln.split(":", 1) for ln in open(path) if ":" in ln and not ln.startswith("#"))
     if fields["source_hash"].strip() == bench.kernel_source_hash():
         assert t == float(fields["traffic_bytes_per_launch"])
     else:
         assert t is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "not-the-profiled-source")
-    assert bench.traffic_for("k_cocg_update", "square256", "mixed16") is None
-    assert bench.traffic_for("k_cocg_update", "no-such-workload", "mixed16") is None
+    assert bench.traffic_for("k_cocg_update", "square256", "mixed16", form) is None
+    assert bench.traffic_for("k_cocg_update", "no-such-workload", "mixed16", form) is None
     assert np.isfinite(float(fields["traffic_bytes_per_launch"]))
