@@ -371,10 +371,7 @@ __device__ __forceinline__ int halo_site(const TileGeom& G, int h, int& dir) {
 // (the neighbour tile, when active, belongs to the same domain and so to
 // the same item and beta).
 __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok) return;
-  // the item state goes out with the unit's data (a unit of a closed item
-  // then leaves with its loads unused)
-  const int state = a.st.done[u.item];
+  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)u.k * NP;
@@ -416,7 +413,6 @@ __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const 
     hpo[j] = ld(a.p_old, kb + hi_[j]);
     hz[j] = ld(a.z, kb + hi_[j]);
   }
-  if (!open_here(state, stencil_mark(it))) return;
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
     const double bn2 = a.st.bn2[u.item];
@@ -508,8 +504,7 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
 // iteration applies the pending alpha_{i-1} p_{i-1}.
 template <typename F, bool REG>
 __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok) return;
-  const int state = a.st.done[u.item];  // checked once the unit's loads are out
+  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   const F* fac = (const F*)a.fac;
@@ -550,10 +545,6 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
   if constexpr (kEarly) load_item_state();
   WaveFactor<F, REG> f;
   f.load(fac, fbase, G.sx, G.sy, u.lane);
-  if (!open_here(state, update_mark(it))) {
-    wait_vm_all();  // the LDS copies land before the wave leaves
-    return;
-  }
   cd mu, unused;
   item_sum(a.partS, 1, a, u, mu, unused);
   if constexpr (!kEarly) load_item_state();

@@ -916,7 +916,15 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
   std::vector<std::string> gerr(G);
   std::vector<std::vector<int>> lsteps_of(P.levels.size());
   const bool verbose = std::getenv("DYSON_VERBOSE") != nullptr;
-  if (G > 1) HIPC(hipEventRecord(w->ev, s));  // d, keys and leaf results are ready
+  if (G > 1) {
+    // d, keys and leaf results are ready: every group's stream waits on the
+    // event here, before any group starts (a group may capture graphs on its
+    // stream, and a wait on an event recorded on a capturing stream fails)
+    HIPC(hipEventRecord(w->ev, s));
+    for (int g = 1; g < G; ++g)
+      if (hipStreamWaitEvent(w->sub_stream[g - 1], w->ev, 0) != hipSuccess)
+        return fail(DYSON_EDEVICE, "level group set-up failed");
+  }
   auto run_group = [&](int g) {
     Work* gw = (g == 0) ? w : w->sub[g - 1].get();
     hipStream_t gs = (g == 0) ? s : w->sub_stream[g - 1];
@@ -933,8 +941,6 @@ dyson_status run_solve(dyson_plan* p, Work* w, const Slice* sl, int n, hipStream
       gw->fac_g[0] = gw->fac_g[1] = -1000;
       gw->prof.reset();
       gw->prof.on = w->prof.on;
-      if (hipStreamWaitEvent(gs, w->ev, 0) != hipSuccess)
-        st = fail(DYSON_EDEVICE, "level group set-up failed");
       launch_zero(gw->gacc, V * sizeof(double), gs);
       if (gw->prof.on) launch_zero(gw->d_prof, 8 * sizeof(unsigned long long), gs);
     }
