@@ -584,6 +584,8 @@ def main():
                          "complement (one inner solve per step) or on X (eqs. (8)-(12))")
     ap.add_argument("--no-other-form", action="store_true",
                     help="skip the one-solve comparison with the other form of the correction")
+    ap.add_argument("--freq-chunk", type=int, default=0,
+                    help="solve the frequencies of a step in calls of this many (0: one call)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and the check")
     ap.add_argument("--cpu-freqs", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true",
@@ -687,9 +689,33 @@ def main():
         f"max m per level={[plan.info.max_m[l] for l in range(plan.info.levels)]}, "
         f"footprint={plan.footprint(w.n_freq) / 2**30:.2f} GiB")
 
+    # a step solves every frequency of the workload; with --freq-chunk C it
+    # does so in consecutive calls of C frequencies (for workloads whose
+    # workspace for all K at once does not fit in HBM)
+    chunk = args.freq_chunk if args.freq_chunk > 0 else w.n_freq
+    spans = [(c0, min(c0 + chunk, w.n_freq)) for c0 in range(0, w.n_freq, chunk)]
+
+    def solve_spans(pl, Gout):
+        rs = []
+        for c0, c1 in spans:
+            t0 = time.perf_counter()
+            _, r = pl.solve(tV, tom[c0:c1], tsig[c0:c1], Gout[c0:c1], report=True)
+            rs.append(r)
+            if len(spans) > 1:
+                torch.cuda.synchronize()
+                log(f"  frequencies {c0}..{c1 - 1}: {time.perf_counter() - t0:.1f} s")
+        if len(rs) == 1:
+            return rs[0]
+        m = dict(rs[0])
+        for k in ("lanczos_steps", "inner_iters", "restarts", "capped_items", "truncated"):
+            m[k] = sum(r[k] for r in rs)
+        for k in ("inner_iters_max", "max_rank_used", "est_rel_err"):
+            m[k] = max(r[k] for r in rs)
+        return m
+
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        plan.solve(tV, tom, tsig, G)
+        solve_spans(plan, G)
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t0:.3f} s")
 
@@ -698,7 +724,7 @@ def main():
     t_start = time.perf_counter()
     for i in range(args.steps):
         t0 = time.perf_counter()
-        _, rep = plan.solve(tV, tom, tsig, G, report=True)
+        rep = solve_spans(plan, G)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
         reports.append(rep)
@@ -708,6 +734,10 @@ def main():
     t_total = time.perf_counter() - t_start
     ms_per_step = 1000.0 * t_total / args.steps
     work = w.n_sites * w.n_freq
+    # the timed plan's workspace goes back before the other legs make theirs
+    plan.close()
+    c0, c1 = spans[0]
+    tom1, tsig1, G1c = tom[c0:c1], tsig[c0:c1], G[c0:c1]
 
     # roofline of the dominant kernel (the inner-solve update, k_cocg_update):
     # algorithmic bytes it moved / its event-timed duration on its stream.  The
@@ -722,13 +752,13 @@ def main():
         pe = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec,
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=1,
                   level_streams=args.level_streams, interface_lanczos=iface)
-        _, r_sh = pe.solve(tV, tom, tsig, G, report=True)
+        _, r_sh = pe.solve(tV, tom1, tsig1, G1c, report=True)
         torch.cuda.synchronize()
         pe.close()
         ms, nb, nl = r_sh["kern_ms"][c], r_sh["kern_bytes"][c], r_sh["kern_launches"][c]
         a_sh = nb / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         # over the whole step: algorithmic bytes of all hot kernel classes / wall time
-        all_b = sum(r_sh["kern_bytes"])
+        all_b = sum(r_sh["kern_bytes"]) * len(spans)  # the first call's, once per call
         path_gbs = all_b / (ms_per_step * 1e-3) / 1e9
         timed = {"level_streams": args.level_streams, "achieved": round(a_sh, 1),
                  "frac": round(a_sh / PEAK_HBM_GBS, 4),
@@ -744,7 +774,7 @@ def main():
                       inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol, profile=2,
                       level_streams=1, interface_lanczos=iface)
             t0 = time.perf_counter()
-            _, r1 = ps.solve(tV, tom, tsig, G, report=True)
+            _, r1 = ps.solve(tV, tom1, tsig1, G1c, report=True)
             torch.cuda.synchronize()
             t1 = time.perf_counter() - t0
             ps.close()
@@ -850,10 +880,10 @@ def main():
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
                   level_streams=args.level_streams, interface_lanczos=iface)
         Gc = torch.empty_like(G)
-        pc.solve(tV, tom, tsig, Gc)
+        solve_spans(pc, Gc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, rc = pc.solve(tV, tom, tsig, Gc, report=True)
+        rc = solve_spans(pc, Gc)
         torch.cuda.synchronize()
         tc = time.perf_counter() - t0
         ec = None
@@ -877,10 +907,10 @@ def main():
                   inner_tol=args.inner_tol, lanczos_tol=args.lanczos_tol,
                   level_streams=args.level_streams, interface_lanczos=1 - iface)
         Go = torch.empty_like(G)
-        po.solve(tV, tom, tsig, Go)
+        solve_spans(po, Go)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, ro = po.solve(tV, tom, tsig, Go, report=True)
+        ro = solve_spans(po, Go)
         torch.cuda.synchronize()
         to = time.perf_counter() - t0
         eo = None
@@ -914,7 +944,8 @@ def main():
                                   else "X form (Lanczos on X, eqs. (8)-(12))"),
                    "lattice": list(w.dims), "n_freq": w.n_freq, "beta": w.beta,
                    "precision": args.precision, "inner_tol": args.inner_tol,
-                   "lanczos_tol": args.lanczos_tol, "parallelism": "1 GPU"},
+                   "lanczos_tol": args.lanczos_tol, "parallelism": "1 GPU",
+                   "frequencies_per_call": chunk},
         "latency_s": {"p50": lat_sorted[len(lat) // 2],
                       "p99": lat_sorted[min(len(lat) - 1, int(0.99 * len(lat)))]},
         "max_rel_err_sampled": err,
