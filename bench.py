@@ -167,7 +167,8 @@ def serve_bench(args):
     def plan_kw(w):
         return dict(t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
                     partition=PART_NESTED, precision=prec, inner_tol=args.inner_tol,
-                    lanczos_tol=args.lanczos_tol)
+                    lanczos_tol=args.lanczos_tol,
+                    interface_lanczos=1 if args.form == "interface" else 0)
 
     # one after the other, blocking calls (plans made before the clock starts)
     ctx0 = Context(0)
@@ -399,7 +400,8 @@ def batch_mix(args):
     def make_plans(ctx):
         return [ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
                          partition=PART_NESTED, precision=PREC_MIXED16, inner_tol=args.inner_tol,
-                         lanczos_tol=args.lanczos_tol, level_streams=args.level_streams)
+                         lanczos_tol=args.lanczos_tol, level_streams=args.level_streams,
+                         interface_lanczos=1 if args.form == "interface" else 0)
                 for w in ws]
 
     # the batch first, on a context of its own (its server's workspaces are
@@ -479,7 +481,8 @@ def serve_sweep(args):
     def plan_kw(w):
         return dict(t=w.t, mu=w.mu, leaf_edge=16 if len(w.dims) == 2 else 6,
                     partition=PART_NESTED, precision=PREC_MIXED16, inner_tol=args.inner_tol,
-                    lanczos_tol=args.lanczos_tol)
+                    lanczos_tol=args.lanczos_tol,
+                    interface_lanczos=1 if args.form == "interface" else 0)
 
     ctx = Context(0)
     plans = {}
