@@ -459,12 +459,14 @@ def test_solve_z_on_the_matsubara_axis_is_solve():
     assert np.array_equal(G1, G2)
 
 
+@pytest.mark.parametrize("iface", [0, 1], ids=["x_form", "interface_form"])
 @pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "mixed16"])
 @pytest.mark.parametrize("dims,s", [((48, 40), 8), ((64, 64), 16), ((10, 9, 8), 4)])
-def test_real_axis_vs_oracle(dims, s, prec):
+def test_real_axis_vs_oracle(dims, s, prec, iface):
     """Energies w + 0.1i across the band: smaller Im H than on the Matsubara axis."""
     V, z, sig, mu, tV, tz, tsig = _real_axis(dims, K=4)
-    p = Plan(dims, t=-1.0, mu=mu, leaf_edge=s, partition=PART_NESTED, precision=prec)
+    p = Plan(dims, t=-1.0, mu=mu, leaf_edge=s, partition=PART_NESTED, precision=prec,
+             interface_lanczos=iface)
     G, rep = p.solve_z(tV, tz, tsig, report=True)
     d = oracle.assemble_diag_z(V, z, sig, mu)
     err = oracle.rel_err(G.cpu().numpy(), oracle.oracle_diag(dims, d, -1.0))

@@ -28,8 +28,8 @@ def _w(dims, K, seed, beta=10.0):
     return synth.rect(dims, K=K, seed=seed, vc=vc, beta=beta)
 
 
-def _plan(ctx, w, s=8, part=0, prec=0):   # nested partition, FP64
-    return ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec)
+def _plan(ctx, w, s=8, part=0, prec=0, **kw):   # nested partition, FP64
+    return ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=s, partition=part, precision=prec, **kw)
 
 
 def test_alone_equals_mix_bitwise():
@@ -315,17 +315,18 @@ def test_fp64_requests_match_solo():
     ctx.close()
 
 
-def test_solve_batch_mixed_lattices():
+@pytest.mark.parametrize("iface", [0, 1], ids=["x_form", "interface_form"])
+def test_solve_batch_mixed_lattices(iface):
     """dyson_solve_batch: square and cubic lattices of different sizes with
     different frequency counts in one blocking call (an uneven batch); each
     result equals its own blocking solve bit for bit and the oracle within
-    1e-10 (FP64)."""
+    1e-10 (FP64), in either form of the correction."""
     ctx = Context(0, slots=3)
     cases = [(_w((48, 33), 3, 31, beta=20.0), 16), (_w((9, 8, 7), 2, 32), 4),
              (_w((37, 29), 4, 33), 8), (_w((12, 12, 12), 2, 34), 6), (_w((64, 64), 5, 35), 16)]
     items, alone, data = [], [], []
     for w, s in cases:
-        p = _plan(ctx, w, s, PART_NESTED, PREC_FP64)
+        p = _plan(ctx, w, s, PART_NESTED, PREC_FP64, interface_lanczos=iface)
         V, om, sig, tV, tom, tsig = device_inputs(w)
         alone.append(p.solve(tV, tom, tsig).cpu().numpy())
         items.append((p, tV, tom, tsig))

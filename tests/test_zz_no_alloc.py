@@ -21,13 +21,15 @@ def _case(dims, K, seed=5):
     return synth.rect(dims, K=K, seed=seed, vc=0.01 * (32.0 / max(dims)) ** 2, beta=20.0)
 
 
-def test_noalloc_matches_solve_twice_then_smaller():
+@pytest.mark.parametrize("iface", [0, 1], ids=["x_form", "interface_form"])
+def test_noalloc_matches_solve_twice_then_smaller(iface):
     w1 = _case((48, 33), K=4)
     w2 = _case((32, 32), K=2, seed=6)
     cases = []
     for w, prec in ((w1, PREC_MIXED16), (w2, PREC_FP64)):
         V, om, sig, tV, tom, tsig = device_inputs(w)
-        p = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=16, precision=prec, level_streams=1)
+        p = Plan(w.dims, t=w.t, mu=w.mu, leaf_edge=16, precision=prec, level_streams=1,
+                 interface_lanczos=iface)
         assert 0 < p.noalloc_bytes(w.n_freq) <= B.dyson_noalloc_max_bytes()
         ref = p.solve(tV, tom, tsig)               # the allocating path, levels in sequence
         G = torch.empty_like(ref)
