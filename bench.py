@@ -486,11 +486,15 @@ def serve_sweep(args):
 
     ctx = Context(0)
     plans = {}
+    prev = None
     t0 = time.perf_counter()
     for i, r in enumerate(reqs):
         w = r["w"]
         if w.dims not in plans:
             plans[w.dims] = ctx.plan(w.dims, **plan_kw(w))
+        if prev is not None and prev is not plans[w.dims]:
+            prev.trim()  # the previous lattice's workspace goes back first
+        prev = plans[w.dims]
         r["alone"] = plans[w.dims].solve(*r["x"])
         torch.cuda.synchronize()
         log(f"alone {i + 1}/{len(reqs)}: {w.name} x {w.n_freq}")

@@ -226,6 +226,13 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat,
                                const dyson_opts* opts, dyson_plan** plan);
 /* DYSON_EBUSY while requests submitted on the plan are not yet released. */
 dyson_status dyson_plan_destroy(dyson_plan* plan);
+/* Gives back the device workspace that the plan's blocking calls (dyson_solve,
+ * dyson_solve_z, dyson_solve_host, dyson_solve_schur and the stage entry
+ * points) keep from one call to the next; the next such call allocates it
+ * again.  The serving slots hold workspaces of their own, which the server
+ * gives back when memory is short.  Must not overlap a blocking call on the
+ * same plan from another thread. */
+dyson_status dyson_plan_trim(dyson_plan* plan);
 dyson_status dyson_plan_get_info(const dyson_plan* plan, dyson_plan_info* info);
 
 /* Host copies of the plan's site maps, natural order, length N each:

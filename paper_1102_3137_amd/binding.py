@@ -88,6 +88,7 @@ SIGNATURES = [
     ("dyson_destroy", C.c_int, [_P]),
     ("dyson_plan_create", C.c_int, [_P, C.POINTER(Lattice), C.POINTER(Opts), C.POINTER(_P)]),
     ("dyson_plan_destroy", C.c_int, [_P]),
+    ("dyson_plan_trim", C.c_int, [_P]),
     ("dyson_plan_get_info", C.c_int, [_P, C.POINTER(PlanInfo)]),
     ("dyson_plan_get_maps", C.c_int, [_P, _I, _I, _I]),
     ("dyson_plan_get_domains", C.c_int, [_P, C.c_int, _I, _I]),
@@ -331,6 +332,10 @@ class Plan:
         self.ctx = self.context.handle
         self.plan = dyson_plan_create(self.ctx, lat, o)
         self.info = dyson_plan_get_info(self.plan)
+
+    def trim(self):
+        """dyson_plan_trim: gives back the workspace kept between blocking calls."""
+        _check(load_library().dyson_plan_trim(self.plan))
 
     def close(self):
         if getattr(self, "plan", None):

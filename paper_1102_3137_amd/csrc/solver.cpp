@@ -1199,6 +1199,13 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
   return DYSON_OK;
 }
 
+dyson_status dyson_plan_trim(dyson_plan* p) {
+  if (!p || !p->ctx) return fail(DYSON_EINVAL, "plan has no device context");
+  HIPC(hipSetDevice(p->ctx->device));
+  free_work(&p->main, nullptr);
+  return DYSON_OK;
+}
+
 dyson_status dyson_plan_destroy(dyson_plan* p) {
   if (!p) return DYSON_OK;
   if (p->live_requests.load() > 0)

@@ -348,3 +348,22 @@ def test_solve_batch_mixed_lattices(iface):
     for it in items:
         it[0].close()
     ctx.close()
+
+
+def test_plan_trim_gives_back_the_workspace():
+    """dyson_plan_trim frees the workspace a plan keeps between blocking
+    calls; the next solve allocates it again and gives the same result."""
+    w = _w((64, 64), 4, 81)
+    V, om, sig, tV, tom, tsig = device_inputs(w)
+    ctx = Context(0)
+    p = _plan(ctx, w, 16, PART_NESTED, PREC_FP64, interface_lanczos=1)
+    G1 = p.solve(tV, tom, tsig)
+    torch.cuda.synchronize()
+    free_held = torch.cuda.mem_get_info()[0]
+    p.trim()
+    free_trim = torch.cuda.mem_get_info()[0]
+    assert free_trim - free_held >= p.footprint(w.n_freq) // 2
+    G2 = p.solve(tV, tom, tsig)
+    assert torch.equal(G1, G2)
+    p.close()
+    ctx.close()

@@ -134,9 +134,11 @@ def test_serving_entry_points_reject_null_handles():
     assert lib.dyson_serve_config(None, 1, 1) == B.EINVAL
     assert lib.dyson_release(None) == B.OK
     plan = _host_plan((16, 16), 8, B.PART_NESTED)
-    # a plan without a device context cannot take requests
+    # a plan without a device context cannot take requests or hold a workspace
     assert lib.dyson_submit(plan, 1, None, None, None, None, 0, B.C.byref(h)) == B.EINVAL
     assert b"device context" in lib.dyson_last_error()
+    assert lib.dyson_plan_trim(plan) == B.EINVAL
+    assert lib.dyson_plan_trim(None) == B.EINVAL
     B.dyson_plan_destroy(plan)
 
 
