@@ -963,6 +963,15 @@ def main():
         "other_correction_form": other,
         "roofline": roof,
         "cpu_baseline": cpu,
+        # the paper's own figures (Sec. III), on its hardware and its 101^2 workload
+        "paper_context": {"hardware": "Cray XT5 Kraken, one processor per frequency "
+                                      "(processor model not stated)",
+                          "workload": "2-D square lattice N = 101^2, 63 Matsubara frequencies",
+                          "low_rank_worst_frequency_s": 28.66,
+                          "gmres_worst_frequency_s": 717.64, "speedup_over_gmres": 25.04,
+                          "low_rank_site_freq_per_s_per_processor": 356,
+                          "note": "context, not the target; the paper's comparison is "
+                                  "preconditioned GMRES on H x = e_i"},
     }
     print(json.dumps(out), flush=True)
 
