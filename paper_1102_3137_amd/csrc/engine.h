@@ -35,6 +35,7 @@ struct DevLevel {
   int* itiles = nullptr;  // tiles holding interface sites of the level, by domain
   int* ilo = nullptr;     // [n] range of each domain in itiles
   int* ihi = nullptr;
+  int* itpos = nullptr;   // [T] position of a tile in itiles, -1 if not listed
   int n_itiles = 0;
 };
 
@@ -142,6 +143,7 @@ struct dyson_plan {
   std::vector<dyson::DevLevel> lv;
   int kcap = 1;     // largest Lanczos step cap + 1 (basis vectors)
   int nmax = 1;     // most domains on one level
+  int nimax = 0;    // most tiles holding one level's interface sites (compact basis)
   int hstride = 1;
   std::vector<int> check_pos;  // tile positions of the sampled error check
   dyson::Work main;  // workspace of the blocking entry points

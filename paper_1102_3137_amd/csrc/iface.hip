@@ -35,6 +35,13 @@ __device__ __forceinline__ bool on_iface(const TileGeom& G, size_t p, int level)
   return G.kind[p] == 2 && G.depth[p] == level;
 }
 
+// Index of site l of tile t in a basis vector of frequency k: compact storage
+// keeps the tiles that hold interface sites only (t must be one of them).
+__device__ __forceinline__ size_t p_at(const LzArgs& a, int k, int t, int l) {
+  return a.qcompact ? ((size_t)k * a.n_tlist + a.tpos[t]) * a.G.S + l
+                    : ((size_t)k * a.G.T + t) * a.G.S + l;
+}
+
 // rhs = E p: on the subdomain sites (graph level + 1) the hopping from the
 // level's interface sites (p vanishes elsewhere).
 __global__ __launch_bounds__(256) void k_f1_rhs(LzArgs a, const double* __restrict__ p,
@@ -51,7 +58,7 @@ __global__ __launch_bounds__(256) void k_f1_rhs(LzArgs a, const double* __restri
       int nt, nl;
       if (!site_nbr(G, t, tid, dir, nt, nl)) continue;
       const size_t np = (size_t)nt * G.S + nl;
-      if (on_iface(G, np, a.level)) acc = cadd(acc, ld(p, kb + np));
+      if (on_iface(G, np, a.level)) acc = cadd(acc, ld(p, p_at(a, k, nt, nl)));
     }
     out = cscale(acc, G.t);
   }
@@ -74,14 +81,14 @@ __global__ __launch_bounds__(256) void k_f1_smat(LzArgs a, const double* __restr
   // p is read on interface sites only: the vector kernels keep it on the
   // interface tiles, and other tiles of the buffer hold stale values
   const bool mine = on_iface(G, pp, a.level);
-  const cd pv = mine ? ld(p, base + tid) : cmk(0.0, 0.0);
+  const cd pv = mine ? ld(p, p_at(a, k, t, tid)) : cmk(0.0, 0.0);
   if (mine) {
     cd acc = cmk(0.0, 0.0);
     for (int dir = 0; dir < 6; ++dir) {
       int nt, nl;
       if (!site_nbr(G, t, tid, dir, nt, nl)) continue;
       const size_t np = (size_t)nt * G.S + nl;
-      if (on_iface(G, np, a.level)) acc = cadd(acc, ld(p, kb + np));
+      if (on_iface(G, np, a.level)) acc = cadd(acc, ld(p, p_at(a, k, nt, nl)));
       else if (active(G.kind[np], G.depth[np], a.level)) acc = csub(acc, ld(u, kb + np));
     }
     out = cfma(ld(d, base + tid), pv, cscale(acc, G.t));

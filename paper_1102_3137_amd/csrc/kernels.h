@@ -83,6 +83,9 @@ struct LzArgs {
   const int* tlist; // tiles the Lanczos vectors live on, grouped by domain, or null
                     // (every tile of the level); the vector kernels run on these only
   int n_tlist;
+  int qcompact;     // 1: the basis vectors and the residual are stored on the listed
+                    // tiles only ([K][n_tlist][S]; other vectors keep [K][T][S])
+  const int* tpos;  // [T] position of a tile in tlist, -1 if not listed (qcompact)
   int n_items;
   unsigned long long* wctr;  // profiling: [2][n_items] algorithmic bytes (CGS update,
                              // CGS products) booked by each item's lead block, or null

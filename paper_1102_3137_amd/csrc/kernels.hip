@@ -273,7 +273,9 @@ __device__ __forceinline__ int lz_tile(const LzArgs& a, int i) { return a.tlist 
   const int item = k * a.n_nodes + node;            \
   if (a.stopped[item]) return;                      \
   const size_t NP = (size_t)a.G.T * a.G.S;          \
-  const size_t base = (size_t)k * NP + (size_t)t * a.G.S;
+  const size_t base = (size_t)k * NP + (size_t)t * a.G.S; \
+  const size_t qb = a.qcompact ? ((size_t)k * a.n_tlist + ti) * a.G.S : base; \
+  (void)qb;
 
 // Start vector: seeded random complex entries (real ones if real_only) on
 // the level's separator sites (the interface C of eq. (4)) of every
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(256) void k_lz_random(LzArgs a, double* __restrict_
       const uint64_t h1 = splitmix64(key), h2 = splitmix64(h1 ^ 0xA5A5A5A5A5A5A5A5ULL);
       v = cmk(2.0 * u01(h1) - 1.0, real_only ? 0.0 : 2.0 * u01(h2) - 1.0);
     }
-    st(q, base + tid, v);
+    st(q, qb + tid, v);
     qq = cmul(v, v);
   }
   block_sum2(qq, un);
@@ -323,7 +325,7 @@ __global__ void k_freq_keys(const double* __restrict__ omega, int zmode, int K,
 __global__ void k_lz_scale(LzArgs a, double* __restrict__ q) {
   LZ_ITEM();
   const cd inv = ld(a.scal, item);
-  if (threadIdx.x < a.G.S) st(q, base + threadIdx.x, cmul(ld(q, base + threadIdx.x), inv));
+  if (threadIdx.x < a.G.S) st(q, qb + threadIdx.x, cmul(ld(q, qb + threadIdx.x), inv));
 }
 
 // Defect of the block solve (eqs. (10)-(12) with the solve of (10) started
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(256) void k_lz_alpha(LzArgs a, const double* __rest
   cd qu = cmk(0.0, 0.0), uu = cmk(0.0, 0.0);
   if (tid < a.G.S) {
     const cd uv = ld(u, base + tid);
-    qu = cmul(ld(q, base + tid), uv);
+    qu = cmul(ld(q, qb + tid), uv);
     uu = cmk(cabs2(uv), 0.0);
   }
   block_sum2(qu, uu);
@@ -381,8 +383,8 @@ __global__ __launch_bounds__(256) void k_lz_recur(LzArgs a, const double* __rest
   const int tid = threadIdx.x;
   if (tid >= a.G.S) return;
   const cd al = ld(a.alpha, item), be = ld(a.beta, item);
-  const cd qv = ld(q, base + tid);
-  const cd qp = qprev ? ld(qprev, base + tid) : cmk(0.0, 0.0);
+  const cd qv = ld(q, qb + tid);
+  const cd qp = qprev ? ld(qprev, qb + tid) : cmk(0.0, 0.0);
   if (D) {  // the X form's streamed diagonal (the interface form takes it at the end)
     cd gv = ld(D, base + tid);
     gv = cadd(gv, cmul(al, cmul(qv, qv)));
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(256) void k_lz_recur(LzArgs a, const double* __rest
   }
   cd rv = csub(ld(u, base + tid), cmul(al, qv));
   rv = csub(rv, cmul(be, qp));
-  st(r, base + tid, rv);
+  st(r, qb + tid, rv);
 }
 
 // Classical Gram-Schmidt, bilinear: h_i = Q_i^T r for i < nvec.  Each wave
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int l = lane + 64 * c;
-    rl[c] = (l < G.S) ? ld(r, base + l) : cmk(0.0, 0.0);
+    rl[c] = (l < G.S) ? ld(r, qb + l) : cmk(0.0, 0.0);
   }
   double* out = a.hpart + ((size_t)k * G.T + t) * (size_t)a.hstride * 2;
   if (pass == 0 && wv == 0) {
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int l = lane + 64 * c;
-      if (l < G.S) acc = cfma(ld(qi, base + l), rl[c], acc);
+      if (l < G.S) acc = cfma(ld(qi, qb + l), rl[c], acc);
     }
     acc = wave_sum(acc);
     if (lane == 0) st(out, i, acc);
@@ -493,13 +495,13 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
     cd acc = cmk(0.0, 0.0);
     for (int i = 0; i < nvec; ++i) {
       const cd hv = (i < 1024) ? hl[i] : ld(hs, i);
-      acc = cfma(hv, ld(Q + (size_t)i * qstride, base + tid), acc);
+      acc = cfma(hv, ld(Q + (size_t)i * qstride, qb + tid), acc);
     }
-    const cd rn = csub(ld(r, base + tid), acc);
-    st(r, base + tid, rn);
+    const cd rn = csub(ld(r, qb + tid), acc);
+    st(r, qb + tid, rn);
     rr = cabs2(rn);
     if (D) {
-      const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, base + tid);
+      const cd qj = ld(Q + (size_t)(nvec - 1) * qstride, qb + tid);
       st(D, base + tid, cfma(acc, qj, ld(D, base + tid)));
     }
   }
@@ -539,7 +541,7 @@ __global__ __launch_bounds__(256) void k_lz_norms(LzArgs a, const double* __rest
   const int tid = threadIdx.x;
   cd rr = cmk(0.0, 0.0), rtr = cmk(0.0, 0.0);
   if (tid < a.G.S) {
-    const cd v = ld(r, base + tid);
+    const cd v = ld(r, qb + tid);
     rr = cmk(cabs2(v), 0.0);
     rtr = cmul(v, v);
   }
@@ -555,7 +557,7 @@ __global__ void k_lz_next(LzArgs a, const double* __restrict__ r, double* __rest
   LZ_ITEM();
   if (threadIdx.x >= a.G.S) return;
   const cd inv = cdiv(cmk(1.0, 0.0), ld(a.beta, item));
-  st(qn, base + threadIdx.x, cmul(ld(r, base + threadIdx.x), inv));
+  st(qn, qb + threadIdx.x, cmul(ld(r, qb + threadIdx.x), inv));
 }
 
 // Per-item scalar steps of the Lanczos recurrence.

@@ -100,6 +100,7 @@ namespace {
 // steps beyond m for m ~ 100; bilinear Lanczos in floating point needs more
 // as m grows (m + 11 observed at m = 128), so the allowance scales as m/8.
 int step_cap(int m, const dyson_opts& o) {
+  if (o.interface_lanczos) return m;  // exactly m steps
   int c = m + std::max(o.extra_steps, (m + 7) / 8);
   if (o.max_rank > 0) c = std::min(c, o.max_rank);
   return c;
@@ -120,12 +121,17 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
                      : (P.opts.precision == DYSON_PREC_MIXED16) ? 2
                                                                 : 8;
   const size_t ni = (size_t)K * p->nmax;
+  // one basis vector: every tile, or (interface form) the tiles holding
+  // interface sites only
+  const size_t qbytes = P.opts.interface_lanczos && p->nimax > 0
+                            ? (size_t)K * p->nimax * P.S * 16
+                            : V;
   std::vector<std::pair<void**, size_t>> t = {
       {(void**)&w->d, V},          {(void**)&w->gacc, V},      {(void**)&w->xB, V},
       {(void**)&w->xH, V},         {(void**)&w->r, V},         {(void**)&w->z, V},
       {(void**)&w->p0, V},         {(void**)&w->p1, V},        {(void**)&w->s, V},
       {(void**)&w->rhs, V},        {(void**)&w->R, V},         {(void**)&w->Dl, V},
-      {(void**)&w->Q, V * nq},     {&w->fac[0], fe * fsz},     {&w->fac[1], fe * fsz},
+      {(void**)&w->Q, qbytes * nq}, {&w->fac[0], fe * fsz},    {&w->fac[1], fe * fsz},
       {(void**)&w->partial, (size_t)K * P.T * 4 * 8},
       {(void**)&w->hpart, (size_t)K * P.T * p->hstride * 16},
       {(void**)&w->h, ni * p->hstride * 16},
@@ -629,7 +635,10 @@ struct Run {
   template <typename Hook>
   void cgs2(const LzArgs& a, const DevLevel& L, int nvec, double* D, Hook after_reduce,
             double eta2 = 0.5) {
-    const size_t qstride = (size_t)K * P().T * P().S * 2;
+    (void)L;
+    // doubles between consecutive basis vectors (compact storage: the listed tiles)
+    const size_t qstride =
+        (size_t)K * (a.qcompact ? (size_t)a.n_tlist : (size_t)P().T) * P().S * 2;
     for (int pass = 0; pass < 2; ++pass) {
       timed(3, [&] { launch_cgs_dot(a, K, w->Q, qstride, nvec, w->R, pass, s); });
       launch_cgs_reduce(a, K, a.tlo, a.thi, nvec, pass, s);
@@ -653,18 +662,21 @@ struct Run {
     const DevLevel& L = p->lv[level];
     const HostPlan& HP = P();
     const size_t V = (size_t)K * HP.T * HP.S * 2;
-    auto Qj = [&](int j) { return w->Q + (size_t)j * V; };
-    auto Vj = [&](int j) { return w->Vb + (size_t)j * V; };
-    CHECKED(reset_items(level));
-    launch_zero(w->Dl, V * sizeof(double), s);
     LzArgs a = lz_args(level);
     a.iface = 1;
-    if (L.n_itiles > 0) {  // the vectors live on the interface tiles only
+    if (L.n_itiles > 0) {  // the basis lives on the interface tiles only, stored compactly
       a.tlist = L.itiles;
       a.n_tlist = L.n_itiles;
       a.tlo = L.ilo;
       a.thi = L.ihi;
+      a.qcompact = 1;
+      a.tpos = L.itpos;
     }
+    const size_t Vq = (size_t)K * (a.qcompact ? (size_t)a.n_tlist : (size_t)HP.T) * HP.S * 2;
+    auto Qj = [&](int j) { return w->Q + (size_t)j * Vq; };
+    auto Vj = [&](int j) { return w->Vb + (size_t)j * V; };
+    CHECKED(reset_items(level));
+    launch_zero(w->Dl, V * sizeof(double), s);
     const int n_items = K * L.n;
     int mm = 0;
     for (int m : HP.levels[level].m) mm = std::max(mm, m);
@@ -1121,6 +1133,20 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
     for (int m : L.m) p->kcap = std::max(p->kcap, step_cap(m, o) + 1);
   }
   p->hstride = p->kcap + 1;
+  // tiles of each level that hold its interface sites (the interface form's
+  // compact basis is sized for the largest count)
+  for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+    int n = 0;
+    for (int t = 0; t < P.T; ++t) {
+      bool has = false;
+      for (int q = 0; q < P.S && !has; ++q) {
+        const size_t pos = (size_t)t * P.S + q;
+        has = P.kind[pos] == KIND_SEP && P.depth[pos] == (int)lev;
+      }
+      n += has;
+    }
+    p->nimax = std::max(p->nimax, n);
+  }
   if (ctx) {
     HIPC(hipSetDevice(ctx->device));
     const size_t TS = (size_t)P.T * P.S;
@@ -1154,6 +1180,10 @@ dyson_status dyson_plan_create(dyson_ctx* ctx, const dyson_lattice* lat, const d
         ihi[nd] = (int)itl.size();
       }
       d.n_itiles = (int)itl.size();
+      std::vector<int> tpos(P.T, -1);
+      for (size_t q = 0; q < itl.size(); ++q) tpos[itl[q]] = (int)q;
+      CHECKED(dalloc(&d.itpos, (size_t)P.T));
+      HIPC(hipMemcpy(d.itpos, tpos.data(), P.T * sizeof(int), hipMemcpyHostToDevice));
       CHECKED(dalloc(&d.itiles, std::max<size_t>(itl.size(), 1)));
       CHECKED(dalloc(&d.ilo, (size_t)L.n_nodes));
       CHECKED(dalloc(&d.ihi, (size_t)L.n_nodes));
@@ -1223,6 +1253,7 @@ dyson_status dyson_plan_destroy(dyson_plan* p) {
       (void)hipFree(d.itiles);
       (void)hipFree(d.ilo);
       (void)hipFree(d.ihi);
+      (void)hipFree(d.itpos);
     }
     (void)hipFree(p->d_nbr);
     (void)hipFree(p->d_kind);
