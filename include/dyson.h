@@ -247,8 +247,10 @@ dyson_status dyson_plan_get_maps(const dyson_plan* plan, int* h_depth,
 /* Interface size m and Lanczos step cap of every correction domain of a
  * level (domains in the order of dyson_correct_level's h_steps): the cap is
  * m + max(extra_steps, ceil(m/8)), or max_rank when that is smaller; a full-rank
- * domain takes between m and cap steps (eqs. (8)-(9): X has rank m).  Either
- * output may be NULL; each has dyson_plan_info.n_nodes[level] entries. */
+ * domain takes between m and cap steps (eqs. (8)-(9): X has rank m).  In the
+ * interface form (interface_lanczos = 1) the cap is m, and every domain takes
+ * exactly m steps.  Either output may be NULL; each has
+ * dyson_plan_info.n_nodes[level] entries. */
 dyson_status dyson_plan_get_domains(const dyson_plan* plan, int level, int* h_m, int* h_cap);
 
 /* Device memory a dyson_solve over K frequencies will allocate (bytes); the
