@@ -313,6 +313,7 @@ dyson_status dyson_solve_z(dyson_plan* plan, int K, const double* d_V, const dou
 #define DYSON_AUTOTUNE_EDGES_2D {8, 12, 16}
 #define DYSON_AUTOTUNE_EDGES_3D {4, 5, 6}
 #define DYSON_AUTOTUNE_LEVEL_STREAMS {1, 3, 4}
+#define DYSON_AUTOTUNE_FORMS {0, 1}
 
 /* The standard domain-decomposition inverse the paper compares against
  * (Sec. II.B, eqs. (4)-(6)): for a one-level decomposition (every separator in
@@ -334,14 +335,16 @@ dyson_status dyson_solve_schur(dyson_plan* plan, int K, const double* d_V, const
                                const double* d_sigma, double* d_G, void* stream,
                                dyson_report* report);
 
-/* Measured choice of the tile shape: for each candidate leaf edge
- * (DYSON_AUTOTUNE_EDGES_2D on chains and squares, DYSON_AUTOTUNE_EDGES_3D on
- * cubes; periodic axes keep only edges that divide them) and level-stream
- * count (DYSON_AUTOTUNE_LEVEL_STREAMS), a plan solves the probe inputs
- * (K frequencies, device pointers as in dyson_solve) once after its
- * workspace is allocated; the fastest wins.  *best = base (NULL: defaults)
- * with leaf_edge and level_streams set; *rate = its site*freq/s.  The probe
- * should be a few representative frequencies of the intended workload. */
+/* Measured choice of the tile shape and the form of the correction: for each
+ * candidate leaf edge (DYSON_AUTOTUNE_EDGES_2D on chains and squares,
+ * DYSON_AUTOTUNE_EDGES_3D on cubes; periodic axes keep only edges that divide
+ * them), level-stream count (DYSON_AUTOTUNE_LEVEL_STREAMS) and form
+ * (DYSON_AUTOTUNE_FORMS as interface_lanczos; only the X form when base sets
+ * max_rank > 0), a plan solves the probe inputs (K frequencies, device
+ * pointers as in dyson_solve) once after its workspace is allocated; the
+ * fastest wins.  *best = base (NULL: defaults) with leaf_edge, level_streams
+ * and interface_lanczos set; *rate = its site*freq/s.  The probe should be a
+ * few representative frequencies of the intended workload. */
 dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyson_opts* base,
                             int K, const double* d_V, const double* d_omega,
                             const double* d_sigma, dyson_opts* best, double* rate);

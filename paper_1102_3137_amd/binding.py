@@ -534,7 +534,7 @@ class Context:
                                              _ptr(Plan._c(omega)), _ptr(Plan._c(sigma)),
                                              C.byref(best), C.byref(rate)))
         return {"leaf_edge": best.leaf_edge, "level_streams": best.level_streams,
-                "rate": rate.value}
+                "interface_lanczos": best.interface_lanczos, "rate": rate.value}
 
     def solve_batch(self, items, report=False):
         """dyson_solve_batch: items = [(plan, V, omega, sigma), ...] with torch

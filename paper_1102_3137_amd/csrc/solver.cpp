@@ -1445,6 +1445,8 @@ dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyso
   std::vector<int> edges = (lat->dim == 3) ? std::vector<int>DYSON_AUTOTUNE_EDGES_3D
                                             : std::vector<int>DYSON_AUTOTUNE_EDGES_2D;
   const std::vector<int> streams = DYSON_AUTOTUNE_LEVEL_STREAMS;
+  std::vector<int> forms = DYSON_AUTOTUNE_FORMS;
+  if (b0.max_rank > 0) forms = {0};  // a truncated rank exists in the X form only
   long long n = 1;
   for (int a = 0; a < 3; ++a) n *= std::max(1, lat->L[a]);
   HIPC(hipSetDevice(ctx->device));
@@ -1454,10 +1456,12 @@ dyson_status dyson_autotune(dyson_ctx* ctx, const dyson_lattice* lat, const dyso
   dyson_status last = DYSON_EINVAL;
   std::string last_err = "no valid candidate";
   for (int e : edges)
-    for (int ls : streams) {
+    for (int ls : streams)
+    for (int f : forms) {
       dyson_opts o = b0;
       o.leaf_edge = e;
       o.level_streams = ls;
+      o.interface_lanczos = f;
       o.profile = 0;
       dyson_plan* p = nullptr;
       if (dyson_plan_create(ctx, lat, &o, &p) != DYSON_OK) continue;  // e.g. periodic extent

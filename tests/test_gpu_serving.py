@@ -236,15 +236,20 @@ def test_autotune_picks_a_valid_tile_shape():
     best = ctx.autotune(w.dims, tV, tom, tsig, t=w.t, mu=w.mu, precision=PREC_MIXED16)
     assert best["leaf_edge"] in _header_list("DYSON_AUTOTUNE_EDGES_2D")
     assert best["level_streams"] in _header_list("DYSON_AUTOTUNE_LEVEL_STREAMS")
+    assert best["interface_lanczos"] in _header_list("DYSON_AUTOTUNE_FORMS")
     assert best["rate"] > 0
     p = ctx.plan(w.dims, t=w.t, mu=w.mu, leaf_edge=best["leaf_edge"], precision=PREC_MIXED16,
-                 level_streams=best["level_streams"])
+                 level_streams=best["level_streams"], interface_lanczos=best["interface_lanczos"])
     G = p.solve(tV, tom, tsig).cpu().numpy()
     assert oracle.rel_err(G, oracle_G(w, V, om, sig)) < 1e-10
     # periodic axes keep only the edges that divide them
     bp = ctx.autotune((48, 48), tV[:48 * 48].contiguous(), tom,
                       tsig[:, :48 * 48].contiguous(), t=w.t, mu=w.mu, periodic=(1, 1))
     assert bp["leaf_edge"] in (8, 12, 16) and 48 % bp["leaf_edge"] == 0
+    # a truncated rank exists in the X form only
+    br = ctx.autotune((32, 32), tV[:32 * 32].contiguous(), tom, tsig[:, :32 * 32].contiguous(),
+                      t=w.t, mu=w.mu, max_rank=16)
+    assert br["interface_lanczos"] == 0
     p.close()
     ctx.close()
 
