@@ -59,6 +59,21 @@ __device__ __forceinline__ Unit decode_id(const CocgLaunch& a, int id) {
   u.item = u.k * a.n_nodes + u.node;
   return u;
 }
+// The stencil and update launches: workgroup b goes to XCD b mod 8, so the
+// 4-tile groups of one frequency are dealt out so that each XCD takes a
+// contiguous range of tiles (tile rows, whose neighbours in the lattice share
+// its L2), while every frequency still spreads over all eight XCDs (the open
+// frequencies come first in the list).  Any tile count that is not a multiple
+// of 32 keeps the plain order.
+__device__ __forceinline__ Unit decode_xcd(const CocgLaunch& a) {
+  const int T = a.G.T;
+  if ((T & 31) != 0) return decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6));
+  const int nW = T / WAVES;  // workgroups per frequency, a multiple of 8
+  const int b = blockIdx.x, ks = b / nW, j = b - ks * nW;
+  const int g = (j & 7) * (nW >> 3) + (j >> 3);
+  return decode_id(a, ks * T + g * WAVES + (threadIdx.x >> 6));
+}
+
 // every unit, one per wave (the initialisation: no list)
 __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
   CocgLaunch b = a;
@@ -493,7 +508,7 @@ __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const 
 // Wave w of workgroup b takes unit b * WAVES + w of the launch's list; the
 // grid covers every unit, and the waves past the list's end leave at once.
 __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
-  stencil_unit(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6)));
+  stencil_unit(a, it, decode_xcd(a));
 }
 
 // r -= alpha s ; z = M^{-1} r ; item totals rho' = r^T z, |r|^2 ; converged
@@ -637,7 +652,7 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
 
 template <typename F, bool REG>
 __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
-  cocg_update_unit<F, REG>(a, it, decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6)));
+  cocg_update_unit<F, REG>(a, it, decode_xcd(a));
 }
 
 template <typename F, bool REG>
