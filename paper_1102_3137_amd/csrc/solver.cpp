@@ -450,12 +450,15 @@ struct Run {
   // COCG on graph g for every item of `level`, x = A_g^{-1} b.  Two launches
   // per iteration; the host polls the device's open-item count only near the
   // iteration count the previous solve of the same kind needed.
-  // Iterations [it0, it0 + n) of an inner solve: stencil, open-frequency
-  // compaction and update per iteration (p_old and p_new trade places).
+  // Iterations [it0, it0 + n) of an inner solve: stencil and update per
+  // iteration (p_old and p_new trade places), and after every fourth stencil
+  // the open-frequency compaction (in between, the list is a superset of the
+  // open frequencies, which only costs the closed units a quick exit).
   void launch_iterations(CocgLaunch c, int it0, int n) {
     for (int i = 0; i < n; ++i) {
       timed(1, [&] { launch_cocg_stencil(c, it0 + i, s); });
-      launch_cocg_compact(c, it0 + i + 2, w->klist, w->d_kcount, s);
+      if (((it0 + i) & 3) == 3)
+        launch_cocg_compact(c, it0 + i + 2, w->klist, w->d_kcount, s);
       timed(0, [&] { launch_cocg_update(c, it0 + i, s); });
       std::swap(c.p_old, c.p_new);
     }
