@@ -21,8 +21,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <algorithm>
-
 #include "devcommon.h"
 #include "kernels.h"
 

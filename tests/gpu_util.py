@@ -41,31 +41,3 @@ def leaf_oracle(w, d_row, plan):
         idx = np.where((tile == tt) & (is_sep == 0))[0]
         out[idx] = np.diag(np.linalg.inv(H[np.ix_(idx, idx)]))
     return out
-
-
-def o3_nd_sites(args):
-    """Worker: O3 (sparse LU of the nested-dissection relabelling, unit solves)
-    at the given sites of one frequency; prints each step as it finishes."""
-    import sys
-    import time
-    import scipy.sparse.linalg as spla
-    from oracle import dyson as od
-    dims, d_row, t, sites, tag = args
-    t0 = time.perf_counter()
-    H = od.hamiltonian(dims, d_row, t)
-    n = H.shape[0]
-    perm = od.nested_dissection_order(dims)
-    where = np.empty_like(perm)
-    where[perm] = np.arange(n)
-    lu = spla.splu(H[perm][:, perm].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.0)
-    print(f"O3 {tag}: factored in {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
-    rows = where[np.asarray(sites)]
-    out = np.empty(len(rows), dtype=np.complex128)
-    for c0 in range(0, len(rows), 32):
-        r = rows[c0:c0 + 32]
-        E = np.zeros((n, len(r)), dtype=np.complex128)
-        E[r, np.arange(len(r))] = 1.0
-        out[c0:c0 + len(r)] = lu.solve(E)[r, np.arange(len(r))]
-        print(f"O3 {tag}: {c0 + len(r)}/{len(rows)} sites, {time.perf_counter() - t0:.0f} s",
-              file=sys.stderr, flush=True)
-    return out
