@@ -123,9 +123,7 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
   const size_t ni = (size_t)K * p->nmax;
   // one basis vector: every tile, or (interface form) the tiles holding
   // interface sites only
-  const size_t qbytes = P.opts.interface_lanczos && p->nimax > 0
-                            ? (size_t)K * p->nimax * P.S * 16
-                            : V;
+  const size_t qbytes = P.opts.interface_lanczos ? (size_t)K * p->nimax * P.S * 16 : V;
   std::vector<std::pair<void**, size_t>> t = {
       {(void**)&w->d, V},          {(void**)&w->gacc, V},      {(void**)&w->xB, V},
       {(void**)&w->xH, V},         {(void**)&w->r, V},         {(void**)&w->z, V},
@@ -667,14 +665,15 @@ struct Run {
     const size_t V = (size_t)K * HP.T * HP.S * 2;
     LzArgs a = lz_args(level);
     a.iface = 1;
-    if (L.n_itiles > 0) {  // the basis lives on the interface tiles only, stored compactly
-      a.tlist = L.itiles;
-      a.n_tlist = L.n_itiles;
-      a.tlo = L.ilo;
-      a.thi = L.ihi;
-      a.qcompact = 1;
-      a.tpos = L.itpos;
-    }
+    // the basis lives on the interface tiles only, stored compactly (every
+    // correction level has interface sites, so the list is never empty)
+    if (L.n_itiles <= 0) return fail(DYSON_EINVAL, "correction level without interface sites");
+    a.tlist = L.itiles;
+    a.n_tlist = L.n_itiles;
+    a.tlo = L.ilo;
+    a.thi = L.ihi;
+    a.qcompact = 1;
+    a.tpos = L.itpos;
     const size_t Vq = (size_t)K * (a.qcompact ? (size_t)a.n_tlist : (size_t)HP.T) * HP.S * 2;
     auto Qj = [&](int j) { return w->Q + (size_t)j * Vq; };
     auto Vj = [&](int j) { return w->Vb + (size_t)j * V; };
