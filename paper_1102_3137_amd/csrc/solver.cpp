@@ -123,7 +123,9 @@ std::vector<std::pair<void**, size_t>> work_table(const dyson_plan* p, Work* w, 
   const size_t ni = (size_t)K * p->nmax;
   // one basis vector: every tile, or (interface form) the tiles holding
   // interface sites only
-  const size_t qbytes = P.opts.interface_lanczos ? (size_t)K * p->nimax * P.S * 16 : V;
+  const size_t qbytes = P.opts.interface_lanczos && p->nimax > 0  // (no levels: unused)
+                            ? (size_t)K * p->nimax * P.S * 16
+                            : V;
   std::vector<std::pair<void**, size_t>> t = {
       {(void**)&w->d, V},          {(void**)&w->gacc, V},      {(void**)&w->xB, V},
       {(void**)&w->xH, V},         {(void**)&w->r, V},         {(void**)&w->z, V},
