@@ -160,7 +160,8 @@ typedef struct {
   long long lanczos_steps;  /* sum over (domain, frequency) of Lanczos steps */
   long long inner_iters;    /* sum over inner solves and items of iterations */
   int inner_iters_max;      /* worst single inner solve */
-  int restarts;             /* breakdown restarts */
+  int restarts;             /* breakdown restarts; in the interface form also the fresh
+                               directions taken after an invariant subspace of S */
   int truncated;            /* 1 if any (domain, frequency) stopped at its step cap
                                (max_rank or m + extra) before the Krylov space of X
                                was exhausted: that result is not full rank */
