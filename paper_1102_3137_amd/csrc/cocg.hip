@@ -86,8 +86,7 @@ __device__ __forceinline__ Unit decode(const CocgLaunch& a) {
 // memory round trip per chunk instead of one per tile.
 template <int CH = 2>
 __device__ __forceinline__ void item_sum_of(const double* part, int per, const CocgLaunch& a,
-                                            int k, int node, int lane, cd& s0, cd& s1) {
-  const int lo = a.tlo[node], hi = a.thi[node];
+                                            int k, int lo, int hi, int lane, cd& s0, cd& s1) {
   s0 = cmk(0.0, 0.0);
   s1 = cmk(0.0, 0.0);
   const size_t kb = (size_t)k * a.G.T;
@@ -100,20 +99,35 @@ __device__ __forceinline__ void item_sum_of(const double* part, int per, const C
       v0[q] = ld(part, qq);
       v1[q] = per == 2 ? ld(part, qq + 1) : cmk(0.0, 0.0);
     }
+    // a select, not a branch: a load used only under a branch would be sunk
+    // into it and cost a round trip of its own
 #pragma unroll
-    for (int q = 0; q < CH; ++q)
-      if (t0 + 64 * q < hi) {
-        s0 = cadd(s0, v0[q]);
-        if (per == 2) s1 = cadd(s1, v1[q]);
-      }
+    for (int q = 0; q < CH; ++q) {
+      const bool in = t0 + 64 * q < hi;
+      s0 = cadd(s0, in ? v0[q] : cmk(0.0, 0.0));
+      if (per == 2) s1 = cadd(s1, in ? v1[q] : cmk(0.0, 0.0));
+    }
   }
   s0 = wave_sum(s0);
   if (per == 2) s1 = wave_sum(s1);
 }
+// The item's state and the tile range of its domain, read together: the
+// three loads depend only on the unit, so they share one memory round trip.
+// The callers pin the range above their state test (an empty asm that uses
+// it): a load used only past a branch is otherwise sunk below it and costs a
+// round trip of its own.
+struct ItemHead {
+  int state, lo, hi;
+};
+__device__ __forceinline__ ItemHead item_head(const CocgLaunch& a, const Unit& u) {
+  const int node = u.ok ? u.node : 0;  // clamped: always a valid index
+  const int item = u.ok ? u.item : 0;
+  return ItemHead{a.st.done[item], a.tlo[node], a.thi[node]};
+}
 template <int CH = 2>
 __device__ __forceinline__ void item_sum(const double* part, int per, const CocgLaunch& a,
-                                         const Unit& u, cd& s0, cd& s1) {
-  item_sum_of<CH>(part, per, a, u.k, u.node, u.lane, s0, s1);
+                                         const Unit& u, const ItemHead& h, cd& s0, cd& s1) {
+  item_sum_of<CH>(part, per, a, u.k, h.lo, h.hi, u.lane, s0, s1);
 }
 
 // ---------------------------------------------------------- tile solve
@@ -218,56 +232,73 @@ struct WaveFactor<F, false> {
 // In place: zl holds r on entry and z = M^{-1} r on exit (tile-local index
 // l = x + sx*y).  Block forward z_y = r_y - T_y S_{y-1}^{-1} z_{y-1}, block
 // backward v_y = S_y^{-1}(z_y - T_{y+1} v_{y+1}), T_y = t diag(active bonds).
-template <typename F, bool REG>
+// The bond mask of T_y costs no test inside the sweeps: an inactive site has
+// the row and column of the identity in every S_y^{-1} (k_factor) and its
+// entry of zl is held at exactly zero (r is zero there and the sweeps write
+// zero there), so a bond to it adds an exact zero.  The reads of a step do
+// not depend on the lane's columns being inside the slice (a column j >= sx
+// meets zero factor entries), so they go out together and the step waits on
+// LDS once.  Lane L owns row i = L>>2: its bits of `am` (bit y: site i + sx*y
+// is active) decide which sites it writes.  SX = 16 fixes the slice width at
+// compile time (full rows of 16x16 tiles, planes of 4^3 tiles): every LDS
+// address of the sweeps is then the lane's base plus an immediate offset,
+// instead of one register per slice; SX = 0 takes the width from sx.
+template <typename F, bool REG, int SX>
 __device__ __forceinline__ void wave_tile_solve(const WaveFactor<F, REG>& f, const F* fac, size_t fbase,
-                                                cd* zl, const uint8_t* act, int sx, int sy,
+                                                cd* zl, const uint8_t* act, int sx_rt, int sy,
                                                 double tt, int lane) {
+  const int sx = SX ? SX : sx_rt;
   const int i = lane >> 2, c = lane & 3;
   wave_sync();
+  unsigned am = 0;
+#pragma unroll
+  for (int y = 0; y < 16; ++y) am |= (act[i + sx * y] ? 1u : 0u) << y;  // i + sx*y <= 255
+  asm volatile("" : "+v"(am));  // one mask register, formed before the sweeps
+  const bool row_lane = c == 0 && i < sx;
 #pragma unroll
   for (int y = 1; y < 16; ++y) {
     if (y < sy) {
+      cd zv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) zv[e] = zl[4 * c + e + sx * (y - 1)];
+      const cd zo = zl[i + sx * y];
       cd acc = cmk(0.0, 0.0);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = 4 * c + e;
-        if (j < sx) acc = cfma(f.get(y - 1, e, fac, fbase, sx, lane), zl[j + sx * (y - 1)], acc);
-      }
+      for (int e = 0; e < 4; ++e) acc = cfma(f.get(y - 1, e, fac, fbase, sx, lane), zv[e], acc);
       acc = quad_sum(acc);
-      if (c == 0 && i < sx) {
-        const int l = i + sx * y;
-        if (act[l] && act[l - sx]) zl[l] = csub(zl[l], cscale(acc, tt));
-      }
+      if (row_lane && ((am >> y) & 1u)) zl[i + sx * y] = csub(zo, cscale(acc, tt));
       wave_sync();
     }
   }
+  // backward: the lane that writes v_y(i) also folds it into the slice below,
+  // z_{y-1}(i) - t v_y(i), which is all that slice's step reads of z_{y-1}
 #pragma unroll
   for (int y = 15; y >= 0; --y) {
     if (y < sy) {
+      cd rw[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rw[e] = zl[4 * c + e + sx * y];
+      const cd zb = zl[i + sx * (y > 0 ? y - 1 : 0)];
       cd acc = cmk(0.0, 0.0);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = 4 * c + e;
-        if (j < sx) {
-          const int l = j + sx * y;
-          cd row = zl[l];
-          if (y < sy - 1 && act[l] && act[l + sx]) row = csub(row, cscale(zl[l + sx], tt));
-          acc = cfma(f.get(y, e, fac, fbase, sx, lane), row, acc);
-        }
-      }
+      for (int e = 0; e < 4; ++e) acc = cfma(f.get(y, e, fac, fbase, sx, lane), rw[e], acc);
       acc = quad_sum(acc);
+      const cd v = ((am >> y) & 1u) ? acc : cmk(0.0, 0.0);
       wave_sync();
-      if (c == 0 && i < sx) zl[i + sx * y] = acc;
+      if (row_lane) {
+        zl[i + sx * y] = v;
+        if (y > 0) zl[i + sx * (y - 1)] = csub(zb, cscale(v, tt));
+      }
       wave_sync();
     }
   }
 }
 
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __device__ __forceinline__ void tile_solve_any(const WaveFactor<F, REG>& f, const F* fac,
                                                size_t fbase, cd* zl, const uint8_t* act,
                                                const TileGeom& G, int lane) {
-  wave_tile_solve<F, REG>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
+  wave_tile_solve<F, REG, SX>(f, fac, fbase, zl, act, G.sx, G.sy, G.t, lane);
 }
 
 // One lane's complex value (16 bytes) copied from global memory into LDS
@@ -299,7 +330,7 @@ __device__ __forceinline__ bool open_here(int state, int mark) {
 // ------------------------------------------------------------- kernels
 // r = b (masked to graph g), x = 0, p = 0, z = M^{-1} r;
 // item totals: rho = r^T z, bn2 = |b|^2
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* __restrict__ b) {
   const Unit u = decode(a);
   if (!u.ok) return;
@@ -314,7 +345,7 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
   const F* fac = (const F*)a.fac;
   const size_t fbase = ((size_t)u.k * G.T + u.t) * (size_t)G.sy * G.sx * G.sx;
   WaveFactor<F, REG> f;
-  f.load(fac, fbase, G.sx, G.sy, u.lane);
+  f.load(fac, fbase, SX ? SX : G.sx, G.sy, u.lane);
   cd rv[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -327,7 +358,7 @@ __global__ __launch_bounds__(256) void k_cocg_init(CocgLaunch a, const double* _
     act[l] = ac ? 1 : 0;
     zl[l] = rv[e];
   }
-  tile_solve_any<F, REG>(f, fac, fbase, zl, act, G, u.lane);
+  tile_solve_any<F, REG, SX>(f, fac, fbase, zl, act, G, u.lane);
   cd rz = cmk(0.0, 0.0), rr = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -384,54 +415,74 @@ __device__ __forceinline__ int halo_site(const TileGeom& G, int h, int& dir) {
 // (the neighbour tile, when active, belongs to the same domain and so to
 // the same item and beta).
 __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
+  if (!u.ok) return;
+  const ItemHead h = item_head(a, u);
   const TileGeom& G = a.G;
+  const int s = G.edge;
+  const int H = 2 * G.dim * (G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s));
+  // The tile's neighbours in the halo directions (slots lane, lane + 64) and
+  // the activity of its own sites depend on the tile alone: a few bytes, read
+  // with the item head so that they share its round trip, and the halo loads
+  // below are not one round trip further back.
+  int hn[2], hown[2], hnl[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int hs = u.lane + 64 * j;
+    int dir = 0;
+    hown[j] = halo_site(G, hs < H ? hs : 0, dir);
+    const int stride = (dir >> 1) == 0 ? 1 : ((dir >> 1) == 1 ? s : s * s);
+    hn[j] = hs < H ? G.nbr[u.t * 6 + dir] : -1;
+    // the neighbour's site (the own face site is a valid stand-in when there is none)
+    hnl[j] = (dir & 1) ? hown[j] - (s - 1) * stride : hown[j] + (s - 1) * stride;
+  }
+  unsigned acm = 0;  // bit e: site lane + 64 e is active in graph g
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = u.lane + 64 * e;
+    const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
+    acm |= (active(G.kind[p], G.depth[p], a.g) && l < G.S) ? (1u << e) : 0u;
+  }
+  asm volatile("" : : "v"(hn[0]), "v"(hn[1]), "v"(acm), "v"(h.lo), "v"(h.hi));  // above the test
+  if (!open_here(h.state, stencil_mark(it))) return;
   const size_t NP = (size_t)G.T * G.S;
   const size_t kb = (size_t)u.k * NP;
   const size_t base = kb + (size_t)u.t * G.S;
-  const bool lead = u.t == a.tlo[u.node];  // records the item state
-  const int s = G.edge;
-  const int H = 2 * G.dim * (G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s));
-  // halo slots h = lane, lane + 64: neighbour tile first (its loads depend on it)
-  int hn[2];
+  const bool lead = u.t == h.lo;  // records the item state
   size_t hi_[2];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int h = u.lane + 64 * j;
-    int dir = 0;
-    const int l = halo_site(G, h < H ? h : 0, dir);
-    const int stride = (dir >> 1) == 0 ? 1 : ((dir >> 1) == 1 ? s : s * s);
-    hn[j] = h < H ? G.nbr[u.t * 6 + dir] : -1;
-    // neighbour site index (own face site as a valid stand-in when there is none)
-    const int nl = (dir & 1) ? l - (s - 1) * stride : l + (s - 1) * stride;
-    hi_[j] = (size_t)u.t * G.S + l;
-    if (hn[j] >= 0) hi_[j] = (size_t)hn[j] * G.S + nl;
-  }
+  for (int j = 0; j < 2; ++j)
+    hi_[j] = hn[j] >= 0 ? (size_t)hn[j] * G.S + hnl[j] : (size_t)u.t * G.S + hown[j];
   bool ac[4];
   cd po[4], zo[4], dv[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int l = u.lane + 64 * e;
     const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
-    ac[e] = active(G.kind[p], G.depth[p], a.g) && l < G.S;
+    ac[e] = (acm >> e) & 1u;
     po[e] = ld(a.p_old, kb + p);
     zo[e] = ld(a.z, kb + p);
     dv[e] = ld(a.d, kb + p);
   }
+  // the halo slots' loads are unconditional (hi_ is always a valid site), so
+  // they go out with the own sites' loads instead of each waiting on a branch
   bool hac[2];
+  uint8_t hk[2], hd[2];
   cd hpo[2], hz[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    hac[j] = hn[j] >= 0 && active(G.kind[hi_[j]], G.depth[hi_[j]], a.g);
+    hk[j] = G.kind[hi_[j]];
+    hd[j] = G.depth[hi_[j]];
     hpo[j] = ld(a.p_old, kb + hi_[j]);
     hz[j] = ld(a.z, kb + hi_[j]);
   }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) hac[j] = (hn[j] >= 0) & active(hk[j], hd[j], a.g);
   cd beta = cmk(0.0, 0.0);
   if (it > 0) {
     const double bn2 = a.st.bn2[u.item];
     const cd rho_prev = ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item);
     cd rho, rr;
-    item_sum<4>(a.partU, 2, a, u, rho, rr);
+    item_sum<4>(a.partU, 2, a, u, h, rho, rr);
     if (a.flush || rr.x <= a.tol2 * bn2) {
       if (it & 1) {  // the last update was even: x still lacks alpha_{i-1} p_{i-1}
         const cd ap = ld(a.alph, u.item);
@@ -452,11 +503,12 @@ __device__ __forceinline__ void stencil_unit(const CocgLaunch& a, int it, const 
   }
   if (lead && u.lane == 0) a.kalive[u.k] = it + 2;  // the item stays open
   // profiling: the item's lead wave books the algorithmic bytes of all the
-  // item's units (one writer per item and launch: no atomics)
+  // item's units; an atomic add that returns nothing, so the wave does not
+  // wait for it (a read-modify-write would add a round trip to the unit)
   if (a.wctr && lead && u.lane == 0)
-    a.wctr[(size_t)1 * a.n_items + u.item] +=
-        (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-        ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
+    atomicAdd(&a.wctr[(size_t)1 * a.n_items + u.item],
+              (unsigned long long)(h.hi - h.lo) *
+                  ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16));
   __shared__ cd psh[WAVES][256];
   __shared__ cd hsh[WAVES][128];
   cd* pl = psh[u.wave];
@@ -515,9 +567,12 @@ __global__ __launch_bounds__(256) void k_cocg_stencil(CocgLaunch a, int it) {
 // p_i (both directions are still resident), on even ones alpha_i is kept for
 // the next; the stencil launch that finds an item converged after an even
 // iteration applies the pending alpha_{i-1} p_{i-1}.
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
+  if (!u.ok) return;
+  const ItemHead h = item_head(a, u);
+  asm volatile("" : : "v"(h.lo), "v"(h.hi));  // the range is read above the state test
+  if (!open_here(h.state, update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   const F* fac = (const F*)a.fac;
@@ -557,9 +612,9 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
   };
   if constexpr (kEarly) load_item_state();
   WaveFactor<F, REG> f;
-  f.load(fac, fbase, G.sx, G.sy, u.lane);
+  f.load(fac, fbase, SX ? SX : G.sx, G.sy, u.lane);
   cd mu, unused;
-  item_sum(a.partS, 1, a, u, mu, unused);
+  item_sum(a.partS, 1, a, u, h, mu, unused);
   if constexpr (!kEarly) load_item_state();
   const bool odd = it & 1;
   if (cabs2(mu) == 0.0) {  // breakdown of the bilinear form in the inner solve
@@ -573,18 +628,19 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
           st(a.x, i, cfma(ap, ld(a.p_old, i), ld(a.x, i)));
         }
     }
-    if (u.t == a.tlo[u.node] && u.lane == 0) a.st.done[u.item] = update_mark(it);
+    if (u.t == h.lo && u.lane == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
   const cd alpha = cdiv(rho, mu);
-  if (u.t == a.tlo[u.node] && u.lane == 0) {
+  if (u.t == h.lo && u.lane == 0) {
     if (!odd) st(a.alph, u.item, alpha);
     // algorithmic bytes: r, s read and r, z written every iteration; x read and
-    // written and p_{i-1}, p_i read on odd ones; the factors
+    // written and p_{i-1}, p_i read on odd ones; the factors (booked as in
+    // the stencil, by an atomic add the wave does not wait for)
     if (a.wctr)
-      a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-                        ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
-                         (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+      atomicAdd(&a.wctr[u.item], (unsigned long long)(h.hi - h.lo) *
+                                     ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
+                                      (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F))));
   }
   // complex64 register factors: the deferred x update in this loop (alpha
   // is then dead during the sweep); otherwise after the sweep, below
@@ -608,7 +664,7 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
     zl[l] = rv;
     rl[l] = rv;
   }
-  tile_solve_any<F, REG>(f, fac, fbase, zl, act, G, u.lane);
+  tile_solve_any<F, REG, SX>(f, fac, fbase, zl, act, G, u.lane);
   cd rz = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -648,20 +704,20 @@ __device__ __forceinline__ void cocg_update_unit(const CocgLaunch& a, int it, co
   }
 }
 
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __device__ __forceinline__ void cocg_update_body(const CocgLaunch& a, int it) {
-  cocg_update_unit<F, REG>(a, it, decode_xcd(a));
+  cocg_update_unit<F, REG, SX>(a, it, decode_xcd(a));
 }
 
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __global__ __launch_bounds__(256) void k_cocg_update(CocgLaunch a, int it) {
-  cocg_update_body<F, REG>(a, it);
+  cocg_update_body<F, REG, SX>(a, it);
 }
 // complex64 register factors: 168 VGPRs, capped for 3 waves per SIMD (the
 // latency of the 2 x 16 slice sweep is what this kernel must hide)
-template <typename F, bool REG>
+template <typename F, bool REG, int SX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_cocg_update_occ3(CocgLaunch a, int it) {
-  cocg_update_body<F, REG>(a, it);
+  cocg_update_body<F, REG, SX>(a, it);
 }
 
 // ------------------------------------------- plane slices: a workgroup per unit
@@ -735,27 +791,30 @@ struct PlaneFactor<double> {
 };
 
 // In place over the workgroup: zl = r on entry, z = M^{-1} r on exit; the
-// same block forward / backward sweeps as wave_tile_solve.
+// same block forward / backward sweeps as wave_tile_solve, with the same
+// test-free treatment of inactive sites (identity rows and columns of
+// S_y^{-1}, zeros in zl) and unconditional reads per step.
 template <typename F>
 __device__ __forceinline__ void plane_tile_solve(const PlaneFactor<F>& f, const F* fac,
                                                  size_t fbase, cd* zl, const uint8_t* act, int n,
                                                  int ns, double tt) {
   const int i = threadIdx.x >> 2, c = threadIdx.x & 3;
   __syncthreads();
+  unsigned am = 0;  // bit y: site i + n*y is active
+#pragma unroll
+  for (int y = 0; y < PNS; ++y) am |= (act[i + n * y] ? 1u : 0u) << y;  // i + n*y <= 243
+  asm volatile("" : "+v"(am));  // one mask register, formed before the sweeps
+  const bool row_thread = c == 0 && i < n;
 #pragma unroll
   for (int y = 1; y < PNS; ++y) {
     if (y < ns) {
       cd acc = cmk(0.0, 0.0);
 #pragma unroll
-      for (int e = 0; e < PW; ++e) {
-        const int j = c * PW + e;
-        if (j < n) acc = cfma(f.get(y - 1, e, fac, fbase, n, i, c), zl[j + n * (y - 1)], acc);
-      }
+      for (int e = 0; e < PW; ++e)
+        acc = cfma(f.get(y - 1, e, fac, fbase, n, i, c), zl[c * PW + e + n * (y - 1)], acc);
+      const cd zo = zl[i + n * y];
       acc = quad_sum(acc);
-      if (c == 0 && i < n) {
-        const int l = i + n * y;
-        if (act[l] && act[l - n]) zl[l] = csub(zl[l], cscale(acc, tt));
-      }
+      if (row_thread && ((am >> y) & 1u)) zl[i + n * y] = csub(zo, cscale(acc, tt));
       __syncthreads();
     }
   }
@@ -764,18 +823,16 @@ __device__ __forceinline__ void plane_tile_solve(const PlaneFactor<F>& f, const 
     if (y < ns) {
       cd acc = cmk(0.0, 0.0);
 #pragma unroll
-      for (int e = 0; e < PW; ++e) {
-        const int j = c * PW + e;
-        if (j < n) {
-          const int l = j + n * y;
-          cd row = zl[l];
-          if (y < ns - 1 && act[l] && act[l + n]) row = csub(row, cscale(zl[l + n], tt));
-          acc = cfma(f.get(y, e, fac, fbase, n, i, c), row, acc);
-        }
-      }
+      for (int e = 0; e < PW; ++e)
+        acc = cfma(f.get(y, e, fac, fbase, n, i, c), zl[c * PW + e + n * y], acc);
+      const cd zb = zl[i + n * (y > 0 ? y - 1 : 0)];
       acc = quad_sum(acc);
+      const cd v = ((am >> y) & 1u) ? acc : cmk(0.0, 0.0);
       __syncthreads();
-      if (c == 0 && i < n) zl[i + n * y] = acc;
+      if (row_thread) {  // v_y(i), and z_{y-1}(i) - t v_y(i) for the next step
+        zl[i + n * y] = v;
+        if (y > 0) zl[i + n * (y - 1)] = csub(zb, cscale(v, tt));
+      }
       __syncthreads();
     }
   }
@@ -834,25 +891,29 @@ __global__ __launch_bounds__(256) void k_cocg_init_planes(CocgLaunch a,
 // The stencil launch of k_cocg_stencil, one thread per site and one halo
 // slot per thread (6 s^2 <= 216 slots).
 __device__ __forceinline__ void stencil_planes_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], stencil_mark(it))) return;
+  if (!u.ok) return;
+  const ItemHead h = item_head(a, u);
   const TileGeom& G = a.G;
-  const size_t NP = (size_t)G.T * G.S;
-  const size_t kb = (size_t)u.k * NP;
-  const size_t base = kb + (size_t)u.t * G.S;
-  const bool lead = u.t == a.tlo[u.node];
   const int s = G.edge;
   const int F = G.dim == 1 ? 1 : (G.dim == 2 ? s : s * s);
   const int H = 2 * G.dim * F;  // <= 216 halo slots (s = 6): one per thread
   const int l = threadIdx.x;
-  // as in k_cocg_stencil: the own site's p_old, z, d and activity and the
-  // thread's halo slot go out before the item reduction
+  // as in k_cocg_stencil: the thread's halo neighbour and its site's activity
+  // are read with the item head; the own site's p_old, z, d and the halo slot
+  // go out before the item reduction
   const size_t p = (size_t)u.t * G.S + (l < G.S ? l : G.S - 1);  // clamped: always valid
   const bool ac = active(G.kind[p], G.depth[p], a.g) && l < G.S;
-  const cd po = ld(a.p_old, kb + p), zo = ld(a.z, kb + p), dv = ld(a.d, kb + p);
   int hdir = 0;
   const int hsite = halo_site(G, l < H ? l : 0, hdir);
   const int hstride = (hdir >> 1) == 0 ? 1 : ((hdir >> 1) == 1 ? s : s * s);
   const int hn = l < H ? G.nbr[u.t * 6 + hdir] : -1;
+  asm volatile("" : : "v"(hn), "v"((int)ac), "v"(h.lo), "v"(h.hi));  // above the state test
+  if (!open_here(h.state, stencil_mark(it))) return;
+  const size_t NP = (size_t)G.T * G.S;
+  const size_t kb = (size_t)u.k * NP;
+  const size_t base = kb + (size_t)u.t * G.S;
+  const bool lead = u.t == h.lo;
+  const cd po = ld(a.p_old, kb + p), zo = ld(a.z, kb + p), dv = ld(a.d, kb + p);
   const size_t hp = hn >= 0 ? (size_t)hn * G.S + ((hdir & 1) ? hsite - (s - 1) * hstride
                                                                : hsite + (s - 1) * hstride)
                             : (size_t)u.t * G.S + hsite;
@@ -863,7 +924,7 @@ __device__ __forceinline__ void stencil_planes_unit(const CocgLaunch& a, int it,
     const double bn2 = a.st.bn2[u.item];
     const cd rho_prev = ld(a.rho2 + (size_t)((it - 1) & 1) * a.n_items * 2, u.item);
     cd rho, rr;
-    item_sum(a.partU, 2, a, u, rho, rr);
+    item_sum(a.partU, 2, a, u, h, rho, rr);
     if (a.flush || rr.x <= a.tol2 * bn2) {
       if ((it & 1) && ac)  // pending alpha_{i-1} p_{i-1} of the deferred x update
         st(a.x, base + l, cfma(ld(a.alph, u.item), po, ld(a.x, base + l)));
@@ -878,9 +939,9 @@ __device__ __forceinline__ void stencil_planes_unit(const CocgLaunch& a, int it,
   }
   if (lead && threadIdx.x == 0) a.kalive[u.k] = it + 2;  // the item stays open
   if (a.wctr && lead && threadIdx.x == 0)
-    a.wctr[(size_t)1 * a.n_items + u.item] +=
-        (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-        ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16);
+    atomicAdd(&a.wctr[(size_t)1 * a.n_items + u.item],
+              (unsigned long long)(h.hi - h.lo) *
+                  ((unsigned long long)(G.S * (5 * 16 + 2)) + 2ull * 2 * (G.sx + G.sy) * 16));
   __shared__ cd pl[256];
   __shared__ cd hl[256];
   const cd pn = ac ? cfma(beta, po, zo) : cmk(0.0, 0.0);
@@ -920,7 +981,10 @@ __global__ __launch_bounds__(256) void k_cocg_stencil_planes(CocgLaunch a, int i
 
 template <typename F>
 __device__ __forceinline__ void update_planes_unit(const CocgLaunch& a, int it, const Unit& u) {
-  if (!u.ok || !open_here(a.st.done[u.item], update_mark(it))) return;
+  if (!u.ok) return;
+  const ItemHead h = item_head(a, u);
+  asm volatile("" : : "v"(h.lo), "v"(h.hi));  // the range is read above the state test
+  if (!open_here(h.state, update_mark(it))) return;
   const TileGeom& G = a.G;
   const size_t base = (size_t)u.k * G.T * G.S + (size_t)u.t * G.S;
   // as in the wave kernel: everything that does not depend on alpha (the
@@ -937,21 +1001,21 @@ __device__ __forceinline__ void update_planes_unit(const CocgLaunch& a, int it, 
   PlaneFactor<F> f;
   f.load(fac, fbase, G.sx, G.sy, threadIdx.x >> 2, threadIdx.x & 3);
   cd mu, unused;
-  item_sum(a.partS, 1, a, u, mu, unused);
+  item_sum(a.partS, 1, a, u, h, mu, unused);
   const bool odd = it & 1;
   if (cabs2(mu) == 0.0) {
     if (odd && ac)
       st(a.x, base + l, cfma(ld(a.alph, u.item), ld(a.p_old, base + l), ld(a.x, base + l)));
-    if (u.t == a.tlo[u.node] && threadIdx.x == 0) a.st.done[u.item] = update_mark(it);
+    if (u.t == h.lo && threadIdx.x == 0) a.st.done[u.item] = update_mark(it);
     return;
   }
   const cd alpha = cdiv(rho, mu);
-  if (u.t == a.tlo[u.node] && threadIdx.x == 0) {
+  if (u.t == h.lo && threadIdx.x == 0) {
     if (!odd) st(a.alph, u.item, alpha);
     if (a.wctr)
-      a.wctr[u.item] += (unsigned long long)(a.thi[u.node] - a.tlo[u.node]) *
-                        ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
-                         (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F)));
+      atomicAdd(&a.wctr[u.item], (unsigned long long)(h.hi - h.lo) *
+                                     ((unsigned long long)(G.S * ((odd ? 8 : 4) * 16 + 2)) +
+                                      (unsigned long long)G.sy * G.sx * G.sx * (2 * sizeof(F))));
   }
   __shared__ cd zl[256];
   __shared__ uint8_t act[256];
@@ -1002,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_cocg_check(CocgLaunch a, int it, int* _
       if (lane == 0) a.st.done[item] = 1;
     } else if (it == 0 || !a.st.done[item]) {
       cd s0, s1;
-      item_sum_of(a.partU, 2, a, k, node, lane, s0, s1);
+      item_sum_of(a.partU, 2, a, k, a.tlo[node], a.thi[node], lane, s0, s1);
       if (it == 0) {
         if (lane == 0) {
           a.st.bn2[item] = s1.x;
@@ -1099,10 +1163,20 @@ void launch_cocg_init(const CocgLaunch& L, const double* b, hipStream_t s) {
     else k_cocg_init_planes<double><<<planes_blocks(L), 256, 0, s>>>(L, b);
     return;
   }
-  // slices of at most 16 sites: a wave per unit, low-precision factors in registers
-  if (L.fp16) k_cocg_init<__half, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
-  else if (L.fp32) k_cocg_init<float, true><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
-  else k_cocg_init<double, false><<<cocg_blocks(L), 64 * WAVES, 0, s>>>(L, b);
+  // slices of at most 16 sites: a wave per unit, low-precision factors in
+  // registers; slices of exactly 16 sites take the fixed-width instance
+  const unsigned nb = cocg_blocks(L);
+  const bool w16 = L.G.sx == 16;
+  if (L.fp16) {
+    if (w16) k_cocg_init<__half, true, 16><<<nb, 64 * WAVES, 0, s>>>(L, b);
+    else k_cocg_init<__half, true, 0><<<nb, 64 * WAVES, 0, s>>>(L, b);
+  } else if (L.fp32) {
+    if (w16) k_cocg_init<float, true, 16><<<nb, 64 * WAVES, 0, s>>>(L, b);
+    else k_cocg_init<float, true, 0><<<nb, 64 * WAVES, 0, s>>>(L, b);
+  } else {
+    if (w16) k_cocg_init<double, false, 16><<<nb, 64 * WAVES, 0, s>>>(L, b);
+    else k_cocg_init<double, false, 0><<<nb, 64 * WAVES, 0, s>>>(L, b);
+  }
 }
 void launch_cocg_stencil(const CocgLaunch& L, int it, hipStream_t s) {
   if (L.G.sx > 16) k_cocg_stencil_planes<<<planes_blocks(L), 256, 0, s>>>(L, it);
@@ -1128,9 +1202,17 @@ void launch_cocg_update(const CocgLaunch& L, int it, hipStream_t s) {
     return;
   }
   const unsigned nb = cocg_blocks(L);
-  if (L.fp16) k_cocg_update<__half, true><<<nb, 64 * WAVES, 0, s>>>(L, it);
-  else if (L.fp32) k_cocg_update_occ3<float, true><<<nb, 64 * WAVES, 0, s>>>(L, it);
-  else k_cocg_update<double, false><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  const bool w16 = L.G.sx == 16;
+  if (L.fp16) {
+    if (w16) k_cocg_update<__half, true, 16><<<nb, 64 * WAVES, 0, s>>>(L, it);
+    else k_cocg_update<__half, true, 0><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  } else if (L.fp32) {
+    if (w16) k_cocg_update_occ3<float, true, 16><<<nb, 64 * WAVES, 0, s>>>(L, it);
+    else k_cocg_update_occ3<float, true, 0><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  } else {
+    if (w16) k_cocg_update<double, false, 16><<<nb, 64 * WAVES, 0, s>>>(L, it);
+    else k_cocg_update<double, false, 0><<<nb, 64 * WAVES, 0, s>>>(L, it);
+  }
 }
 
 }  // namespace dyson

@@ -407,9 +407,10 @@ __global__ __launch_bounds__(256) void k_cgs_dot(LzArgs a, const double* __restr
   if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])
-    a.wctr[(size_t)1 * a.n_items + item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
-                                            ((unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec);
+  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])  // non-returning: nothing waits on it
+    atomicAdd(&a.wctr[(size_t)1 * a.n_items + item],
+              (unsigned long long)(a.thi[node] - a.tlo[node]) *
+                  ((unsigned long long)(nvec + 1) * G.S * 16 + 16ull * nvec));
   cd rl[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -482,9 +483,9 @@ __global__ __launch_bounds__(256) void k_cgs_update(LzArgs a, const double* __re
   LZ_ITEM();
   if (pass == 1 && !a.reorth[item]) return;
   const TileGeom& G = a.G;
-  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])
-    a.wctr[item] += (unsigned long long)(a.thi[node] - a.tlo[node]) *
-                    ((unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec);
+  if (a.wctr && threadIdx.x == 0 && ti == a.tlo[node])  // non-returning: nothing waits on it
+    atomicAdd(&a.wctr[item], (unsigned long long)(a.thi[node] - a.tlo[node]) *
+                                 ((unsigned long long)(nvec + 4) * G.S * 16 + 16ull * nvec));
   __shared__ cd hl[1024];
   const double* hs = a.h + (size_t)item * a.hstride * 2;
   for (int i = threadIdx.x; i < nvec && i < 1024; i += blockDim.x) hl[i] = ld(hs, i);
