@@ -63,11 +63,17 @@ __device__ __forceinline__ Unit decode_id(const CocgLaunch& a, int id) {
 // its L2), while every frequency still spreads over all eight XCDs (the open
 // frequencies come first in the list).  Any tile count that is not a multiple
 // of 32 keeps the plain order.
+// A workgroup whose frequency slot lies past the list's end leaves after the
+// one scalar load of the list length, before any vector load: in the late
+// launches of a solve most of the grid is such workgroups.
 __device__ __forceinline__ Unit decode_xcd(const CocgLaunch& a) {
   const int T = a.G.T;
   if ((T & 31) != 0) return decode_id(a, blockIdx.x * WAVES + (threadIdx.x >> 6));
   const int nW = T / WAVES;  // workgroups per frequency, a multiple of 8
   const int b = blockIdx.x, ks = b / nW, j = b - ks * nW;
+  if (a.klist && ks >= *a.kcount) {
+    return Unit{0, 0, -1, -1, (int)(threadIdx.x & 63), (int)(threadIdx.x >> 6), false};
+  }
   const int g = (j & 7) * (nW >> 3) + (j >> 3);
   return decode_id(a, ks * T + g * WAVES + (threadIdx.x >> 6));
 }
