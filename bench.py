@@ -44,13 +44,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_only(text):
+    """C/C++ source text without its comments, trailing blanks and empty lines
+    (string and character literals are kept whole)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = [ln.rstrip() for ln in "".join(out).splitlines()]
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash():
-    """Hash of the sources that define the dominant kernel (k_cocg_update):
-    counter-derived traffic is reported only for the kernel version the
-    counters were taken on."""
+    """Hash of the code (comments and blank lines excluded) of the sources
+    that define the dominant kernel (k_cocg_update): counter-derived traffic
+    is reported only for the kernel version the counters were taken on."""
     h = hashlib.sha256()
     for f in ["cocg.hip", "devcommon.h", "kernels.h"]:
-        h.update(open(os.path.join(ROOT, "paper_1102_3137_amd", "csrc", f), "rb").read())
+        with open(os.path.join(ROOT, "paper_1102_3137_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode("utf-8"))
     return h.hexdigest()[:16]
 
 

@@ -53,8 +53,8 @@ struct CocgLaunch {
   double tol2;           // squared relative residual target
   int flush;             // final stencil launch: close every open item
   const int* klist;      // frequencies with an open item (compacted), or null: every
-                         // frequency; the stencil and update launches loop over
-                         // the units of these only (persistent grid)
+                         // frequency; the stencil and update launches map their units
+                         // through it, and the units past its length leave at once
   const int* kcount;     // [1] length of klist
   int* kalive;           // [K] stamp of the last launch after which frequency k still
                          // had an open item (1: the initial check, it + 2: stencil it)

@@ -52,3 +52,12 @@ def test_traffic_is_reported_only_for_the_profiled_source(monkeypatch, form):
     assert bench.traffic_for("k_cocg_update", "square256", "mixed16", form) is None
     assert bench.traffic_for("k_cocg_update", "no-such-workload", "mixed16", form) is None
     assert np.isfinite(float(fields["traffic_bytes_per_launch"]))
+
+
+def test_kernel_source_hash_ignores_comments_only():
+    """The profiles are keyed by the kernels' code: a comment edit keeps them
+    valid, a code edit does not."""
+    src = 'int a = 1;  // note\n/* block\n   comment */\nconst char* s = "x // y";\n'
+    assert bench.code_only(src) == 'int a = 1;\nconst char* s = "x // y";'
+    assert bench.code_only(src.replace("note", "other").replace("block", "b")) == bench.code_only(src)
+    assert bench.code_only(src.replace("= 1", "= 2")) != bench.code_only(src)
