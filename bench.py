@@ -600,7 +600,7 @@ def main():
                     default="square256")
     ap.add_argument("--freqs", type=int, default=0,
                     help="use only the first K frequencies of the workload (0 = all)")
-    ap.add_argument("--level-streams", type=int, default=3,
+    ap.add_argument("--level-streams", type=int, default=6,
                     help="concurrent correction-level groups (1 = bottom-up, least memory)")
     ap.add_argument("--inner-tol", type=float, default=1e-11,
                     help="relative residual of the inner solves (1e-11: about 1e-9 from "

@@ -156,11 +156,11 @@ def test_interface_form_large_lattice(L, freqs, prec):
 
 def test_interface_form_bench_configuration_256():
     """The throughput workload's settings (complex32 factors, inner solves to
-    1e-11, three concurrent level groups) in the interface form."""
+    1e-11, six concurrent level groups) in the interface form."""
     w = synth.Workload(dims=(256, 256), t=-1.0, mu=0.5, vc=2e-4, beta=20.0,
                        freq_index=(0, 31, 63), seed=2, name="square 256")
     V, om, sig, tV, tom, tsig = device_inputs(w)
-    p = _plan(w, 16, 0, PREC_MIXED16, inner_tol=1e-11, lanczos_tol=1e-11, level_streams=3)
+    p = _plan(w, 16, 0, PREC_MIXED16, inner_tol=1e-11, lanczos_tol=1e-11, level_streams=6)
     G, rep = p.solve(tV, tom, tsig, report=True)
     err = oracle.rel_err(G.cpu().numpy(), oracle_G(w, V, om, sig, method="rgf"))
     print(f"iface bench configuration err={err:.2e} rep={rep}", flush=True)

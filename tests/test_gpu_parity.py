@@ -256,7 +256,7 @@ def test_solve_large_lattice(L, freqs, prec):
 def test_bench_configuration_256():
     """The throughput workload exactly as the benchmark runs it: 256^2, 16x16
     tiles, recursive bisection, complex32 preconditioner factors, inner solves
-    to 1e-11, Lanczos 1e-11, three concurrent level groups; frequencies
+    to 1e-11, Lanczos 1e-11, six concurrent level groups; frequencies
     w_0, w_31 and w_63 of the beta = 20 grid, every site against the
     block-tridiagonal oracle.  The metric counts results within 1e-6; at
     this inner tolerance the method lands near 1e-9, asserted below the
@@ -264,7 +264,7 @@ def test_bench_configuration_256():
     w = synth.Workload(dims=(256, 256), t=-1.0, mu=0.5, vc=2e-4, beta=20.0,
                        freq_index=(0, 31, 63), seed=2, name="square 256")
     V, om, sig, tV, tom, tsig = device_inputs(w)
-    p = _plan(w, 16, 0, PREC_MIXED16, inner_tol=1e-11, lanczos_tol=1e-11, level_streams=3)
+    p = _plan(w, 16, 0, PREC_MIXED16, inner_tol=1e-11, lanczos_tol=1e-11, level_streams=6)
     G, rep = p.solve(tV, tom, tsig, report=True)
     err = oracle.rel_err(G.cpu().numpy(), oracle_G(w, V, om, sig, method="rgf"))
     print(f"bench configuration err={err:.2e} rep={rep}")
